@@ -1,0 +1,164 @@
+"""CPU oracle for the acceptance-rejection selector -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+import this package.  The product (``paper_1404_0027_amd``) never does, and
+this package never imports the product: the two share no code.
+
+``arsel_oracle.c`` holds the plain sequential algorithms (Philox4x32-10,
+uniform and proposal acceptance-rejection with the exact inverse-transform
+fallback, mass-action propensities, the SSA jump chain); this module wraps
+them with ctypes and numpy arrays.  ``laws.py`` holds closed forms used to
+pin them; ``mlp.py`` the numpy forward/backward of the learned proposal.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "arsel_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+          "-shared", "-fPIC", "-Wall", "-Wextra"]
+
+
+def build() -> str:
+    """Compile the oracle library with gcc (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, u64, u32, i32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_philox4x32_10.restype = None
+        L.orc_select_uniform.argtypes = [P, i64, i64, i64, i32, P, u64, u64, u32, u32, P, P, P, i32]
+        L.orc_select_uniform.restype = i32
+        L.orc_select_ragged.argtypes = [P, P, i64, u64, u64, u32, P, P, P, i32]
+        L.orc_select_ragged.restype = i32
+        L.orc_select_proposal.argtypes = [P, P, i64, i64, i64, i64, u64, u64, u32, P, P, i32]
+        L.orc_select_proposal.restype = i32
+        L.orc_propensities.argtypes = [P, i64, i64, i64, P, P, P, P]
+        L.orc_propensities.restype = None
+        L.orc_ssa_chain.argtypes = [P, i64, i64, i64, P, P, P, P, P, u64, u64, i64, u32, i64,
+                                    P, P, i32]
+        L.orc_ssa_chain.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+AOS, SOA = 0, 1
+DEBUG_CHECK_BOUND = 1
+TAG_UNIFORM, TAG_PROPOSAL, TAG_SSA = 0, 1, 2
+FALLBACK_WORD = 0xFFFFFFFF
+
+
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of one counter (4 x u32) under one key (2 x u32)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def draw(seed: int, word0: int, inst: int, step: int, tag: int) -> np.ndarray:
+    """The four words of one trial: counter (word0, inst, step lo, step hi ^ tag<<28)."""
+    ctr = [word0 & 0xFFFFFFFF, inst & 0xFFFFFFFF, step & 0xFFFFFFFF,
+           ((step >> 32) ^ (tag << 28)) & 0xFFFFFFFF]
+    return philox(ctr, [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF])
+
+
+def select_uniform(alpha: np.ndarray, M: int, K: int, ld: int, layout: int = AOS, *,
+                   seed: int, step: int = 0, t_max: int = 4096, bound=None, flags: int = 0,
+                   want_alpha0: bool = True, want_trials: bool = True, threads: int = 1):
+    """Sequential uniform AR for K instances.  Returns (index, alpha0, trials)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float32)
+    b = None if bound is None else np.ascontiguousarray(bound, dtype=np.float32)
+    idx = np.empty(K, dtype=np.int32)
+    a0 = np.empty(K, dtype=np.float32) if want_alpha0 else None
+    tr = np.empty(K, dtype=np.uint32) if want_trials else None
+    rc = lib().orc_select_uniform(_p(a), M, K, ld, layout, _p(b), seed, step, t_max, flags,
+                                  _p(idx), _p(a0), _p(tr), threads)
+    if rc != 0:
+        raise ValueError(f"orc_select_uniform rejected its arguments ({rc})")
+    return idx, a0, tr
+
+
+def select_ragged(alpha: np.ndarray, offsets: np.ndarray, *, seed: int, step: int = 0,
+                  t_max: int = 4096, want_alpha0: bool = True, want_trials: bool = True,
+                  threads: int = 1):
+    a = np.ascontiguousarray(alpha, dtype=np.float32)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    K = off.shape[0] - 1
+    idx = np.empty(K, dtype=np.int32)
+    a0 = np.empty(K, dtype=np.float32) if want_alpha0 else None
+    tr = np.empty(K, dtype=np.uint32) if want_trials else None
+    rc = lib().orc_select_ragged(_p(a), _p(off), K, seed, step, t_max, _p(idx), _p(a0),
+                                 _p(tr), threads)
+    if rc != 0:
+        raise ValueError("orc_select_ragged rejected its arguments")
+    return idx, a0, tr
+
+
+def select_proposal(alpha: np.ndarray, Q: np.ndarray, *, seed: int, step: int = 0,
+                    t_max: int = 4096, threads: int = 1):
+    """alpha float32 [K, M], Q uint32 [K, M].  Returns (index, trials)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float32)
+    q = np.ascontiguousarray(Q, dtype=np.uint32)
+    K, M = a.shape
+    idx = np.empty(K, dtype=np.int32)
+    tr = np.empty(K, dtype=np.uint32)
+    rc = lib().orc_select_proposal(_p(a), _p(q), M, K, M, M, seed, step, t_max, _p(idx),
+                                   _p(tr), threads)
+    if rc != 0:
+        raise ValueError("orc_select_proposal rejected its arguments")
+    return idx, tr
+
+
+def propensities(net, X: np.ndarray) -> np.ndarray:
+    """Mass-action propensities alpha[r, j] of states X[r, i] (int32)."""
+    x = np.ascontiguousarray(X, dtype=np.int32)
+    R, N = x.shape
+    M = int(net.r0.shape[0])
+    out = np.empty((R, M), dtype=np.float32)
+    lib().orc_propensities(_p(x), R, N, M, _p(np.ascontiguousarray(net.r0, np.int32)),
+                           _p(np.ascontiguousarray(net.r1, np.int32)),
+                           _p(np.ascontiguousarray(net.rate, np.float32)), _p(out))
+    return out
+
+
+def ssa_chain(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: int = 4096,
+              rec_from: int | None = None, threads: int = 1):
+    """Run the jump chain.  Returns (X_final, recorded states or None, fired[steps, R])."""
+    x = np.array(X0, dtype=np.int32, copy=True, order="C")
+    R, N = x.shape
+    M = int(net.r0.shape[0])
+    rec = None
+    if rec_from is not None:
+        rec = np.empty((steps - rec_from, R, N), dtype=np.int32)
+    fired = np.empty((steps, R), dtype=np.int32)
+    arrs = [np.ascontiguousarray(v, np.int32) for v in (net.r0, net.r1, net.p0, net.p1)]
+    rate = np.ascontiguousarray(net.rate, np.float32)
+    lib().orc_ssa_chain(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), seed, step0, steps,
+                        t_max, 0 if rec_from is None else rec_from, _p(rec), _p(fired), threads)
+    return x, rec, fired

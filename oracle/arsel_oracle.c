@@ -1,0 +1,444 @@
+/*
+ * arsel CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, sequential, obviously-correct CPU implementation of what the
+ * selection path computes.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library; the product path never
+ * does.  It shares no code, header or table with the HIP sources.
+ *
+ * What it follows (Neri & Mestivier, "An efficient GPU acceptance-rejection
+ * algorithm for the selection of the next reaction to occur for Stochastic
+ * Simulation Algorithms", arXiv:1404.0027):
+ *
+ *  - Section "A GPU acceptance-rejection algorithm (GPU/AR) for SSA", first
+ *    paragraph: the sequential acceptance-rejection rule -- draw a reaction
+ *    index j uniformly and a uniform u in [0,T) until u < alpha_j; the first
+ *    accepted candidate is the next reaction.  Here T = alpha_max (or a
+ *    caller-supplied bound >= alpha_max), and the draw sequence is indexed by
+ *    an explicit trial counter t = 0, 1, ... so the answer is "the accepted
+ *    candidate with the least t".  Trials are capped at t_max.
+ *  - Section "The Stochastic Simulation Algorithm": the inverse-transform
+ *    rule (least j whose cumulative propensity exceeds r * alpha_0), used
+ *    here, in exact fixed-point integers, as the fallback when t_max trials
+ *    all reject.
+ *  - Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+ *    random numbers: as easy as 1, 2, 3", SC'11), written here from that
+ *    published definition.  The paper itself only names the GPU generators
+ *    it used (section "Materials").
+ *  - Section "The Stochastic Simulation Algorithm" again for the SSA state
+ *    update X <- X + v_j used by the jump-chain data generator.
+ *
+ * Readings where the paper is silent are listed in the design notes; the
+ * ones that fix arithmetic here: u lives on the 53-bit grid {0, 2^-53, ...,
+ * 1 - 2^-53} and the product u*alpha_max is one binary64 multiply (a 24-bit
+ * float grid would over-weight reactions with alpha_j < 2^-24 alpha_max);
+ * acceptance is strict (u*alpha_max < alpha_j); candidates are
+ * exactly uniform (Lemire multiply-shift with its rejection folded into the
+ * trial); indexes are 0-based; -1 means every propensity is zero and -2 an
+ * invalid (NaN, negative, +inf) propensity.
+ *
+ * Build: gcc -O2 -std=gnu11 -ffp-contract=off -fopenmp -shared -fPIC.  No
+ * fast-math, default MXCSR (no FTZ/DAZ), so every float op is one IEEE op.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (SC'11): counter c[4], key k[2]; 10 rounds; after each */
+/* round the key is bumped by the two Weyl constants.                   */
+/* ------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += PHILOX_W0;
+        k1 += PHILOX_W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Counter layout of one random draw: (word0, instance, step lo, step hi ^ tag<<28).
+ * Tags: 0 uniform select, 1 proposal select, 2 SSA data generation.
+ * word0 is the trial index; 0xFFFFFFFF is reserved for the fallback draw. */
+#define FALLBACK_WORD 0xFFFFFFFFu
+
+static void draw(uint64_t seed, uint32_t word0, uint32_t inst, uint64_t step,
+                 uint32_t tag, uint32_t out[4])
+{
+    uint32_t ctr[4] = { word0, inst, (uint32_t)step,
+                        (uint32_t)(step >> 32) ^ (tag << 28) };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* u on the 53-bit grid {0, 2^-53, ..., 1 - 2^-53}: 32 bits of w1 above the
+ * top 21 bits of w2.  Both terms and their sum are exact in binary64. */
+static double grid_u(uint32_t w1, uint32_t w2)
+{
+    return (double)w1 * 0x1p-32 + (double)(w2 >> 11) * 0x1p-53;
+}
+
+/* L = ceil(log2 M), 0 for M = 1. */
+static int ceil_log2(int64_t M)
+{
+    int L = 0;
+    while (((int64_t)1 << L) < M) ++L;
+    return L;
+}
+
+/* ------------------------------------------------------------------ */
+/* Exact inverse-transform fallback in fixed point.                    */
+/* F_j = floor(alpha_j * 2^(63-L-E)) with 2^(E-1) <= alpha_max < 2^E.   */
+/* Each F_j < 2^(63-L), so S = sum F_j < 2^63.  target = floor(V*S/2^64) */
+/* for a 64-bit uniform V; the answer is the least j whose inclusive    */
+/* prefix sum exceeds target.                                          */
+/* ------------------------------------------------------------------ */
+static uint64_t fixed_weight(float a, int shift)
+{
+    return (uint64_t)ldexpf(a, shift);
+}
+
+static uint64_t fixed_sum(const float *a, int64_t stride, int64_t M, int shift)
+{
+    uint64_t S = 0;
+    for (int64_t j = 0; j < M; ++j) S += fixed_weight(a[j * stride], shift);
+    return S;
+}
+
+static int32_t fallback_pick(const float *a, int64_t stride, int64_t M, int shift,
+                             uint64_t S, uint64_t V)
+{
+    uint64_t target = (uint64_t)(((unsigned __int128)V * S) >> 64);
+    uint64_t P = 0;
+    for (int64_t j = 0; j < M; ++j) {
+        P += fixed_weight(a[j * stride], shift);
+        if (P > target) return (int32_t)j;
+    }
+    return -1; /* unreachable when S > 0 */
+}
+
+/* alpha_0 reported from the fixed-point sum: (float)S rounded to nearest even,
+ * scaled back by 2^(E-63+L). */
+static float fixed_alpha0(uint64_t S, int shift)
+{
+    return ldexpf((float)S, -shift);
+}
+
+/* Scan: validity and exact maximum.  Returns 0 ok, -2 invalid. */
+static int scan_max(const float *a, int64_t stride, int64_t M, float *amax)
+{
+    float m = 0.0f;
+    for (int64_t j = 0; j < M; ++j) {
+        float x = a[j * stride];
+        if (!(x >= 0.0f) || x == INFINITY) return -2;
+        if (x > m) m = x;
+    }
+    *amax = m;
+    return 0;
+}
+
+/* flags */
+#define ORC_DEBUG_CHECK_BOUND 1u
+
+/* ------------------------------------------------------------------ */
+/* Uniform-proposal AR, one instance.                                   */
+/* ------------------------------------------------------------------ */
+static int32_t select_uniform_one(const float *a, int64_t stride, int64_t M,
+                                  const float *bound, uint32_t flags, uint32_t k,
+                                  uint64_t seed, uint64_t step, uint32_t tag,
+                                  uint32_t t_max, float *alpha0, uint32_t *trials)
+{
+    float amax = 0.0f, env;
+    int have_max = 0;
+    if (trials) *trials = 0;
+    if (bound == NULL || (flags & ORC_DEBUG_CHECK_BOUND) || alpha0 != NULL) {
+        if (scan_max(a, stride, M, &amax) != 0) {
+            if (alpha0) *alpha0 = NAN;
+            return -2;
+        }
+        have_max = 1;
+    }
+    if (bound != NULL) {
+        env = *bound;
+        if (env != env || env < 0.0f || env == INFINITY) {
+            if (alpha0) *alpha0 = NAN;
+            return -2;
+        }
+        if (have_max && (flags & ORC_DEBUG_CHECK_BOUND) && amax > env) {
+            if (alpha0) *alpha0 = NAN;
+            return -3;
+        }
+        if (env == 0.0f) {
+            if (alpha0) *alpha0 = 0.0f;
+            return -1;
+        }
+    } else {
+        env = amax;
+    }
+    int L = ceil_log2(M);
+    if (have_max) {
+        if (amax == 0.0f) {
+            if (alpha0) *alpha0 = 0.0f;
+            return -1;
+        }
+        if (alpha0) {
+            int E;
+            frexpf(amax, &E);
+            *alpha0 = fixed_alpha0(fixed_sum(a, stride, M, 63 - L - E), 63 - L - E);
+        }
+    }
+
+    /* The sequential rule: trials t = 0, 1, ...; the first accepted wins. */
+    uint32_t lemire_floor = (uint32_t)(0u - (uint32_t)M) % (uint32_t)M; /* 2^32 mod M */
+    for (uint32_t t = 0; t < t_max; ++t) {
+        uint32_t w[4];
+        draw(seed, t, k, step, tag, w);
+        uint64_t m = (uint64_t)w[0] * (uint64_t)M;
+        if ((uint32_t)m < lemire_floor) continue;  /* candidate draw rejected */
+        int64_t j = (int64_t)(m >> 32);
+        double u = grid_u(w[1], w[2]);
+        if (u * (double)env < (double)a[j * stride]) {
+            if (trials) *trials = t + 1;
+            return (int32_t)j;
+        }
+    }
+
+    /* Fallback: exact inverse transform on the true maximum. */
+    if (!have_max) {
+        if (scan_max(a, stride, M, &amax) != 0) return -2;
+        if (amax == 0.0f) return -1;
+    }
+    int E;
+    frexpf(amax, &E);
+    int shift = 63 - L - E;
+    uint64_t S = fixed_sum(a, stride, M, shift);
+    uint32_t w[4];
+    draw(seed, FALLBACK_WORD, k, step, tag, w);
+    uint64_t V = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    if (trials) *trials = t_max + 1;
+    return fallback_pick(a, stride, M, shift, S, V);
+}
+
+/* Dense batch.  layout 0 (AoS): alpha[k*ld + j] (ld = 0 broadcasts one vector);
+ * layout 1 (SoA): alpha[j*ld + k].  bound: NULL or K per-instance bounds. */
+int orc_select_uniform(const float *alpha, int64_t M, int64_t K, int64_t ld, int layout,
+                       const float *bound, uint64_t seed, uint64_t step, uint32_t t_max,
+                       uint32_t flags, int32_t *index, float *alpha0, uint32_t *trials,
+                       int threads)
+{
+    if (M < 1 || K < 0 || (layout != 0 && layout != 1)) return -1;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 16) if (threads != 1)
+#endif
+    for (int64_t k = 0; k < K; ++k) {
+        const float *a;
+        int64_t stride;
+        if (layout == 0) { a = alpha + k * ld; stride = 1; }
+        else             { a = alpha + k;      stride = ld; }
+        index[k] = select_uniform_one(a, stride, M, bound ? bound + k : NULL, flags,
+                                      (uint32_t)k, seed, step, 0u, t_max,
+                                      alpha0 ? alpha0 + k : NULL,
+                                      trials ? trials + k : NULL);
+    }
+    return 0;
+}
+
+/* Ragged batch: instance k is alpha[offsets[k] .. offsets[k+1]). */
+int orc_select_ragged(const float *alpha, const int64_t *offsets, int64_t K,
+                      uint64_t seed, uint64_t step, uint32_t t_max,
+                      int32_t *index, float *alpha0, uint32_t *trials, int threads)
+{
+    if (K < 0) return -1;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 1) if (threads != 1)
+#endif
+    for (int64_t k = 0; k < K; ++k) {
+        int64_t M = offsets[k + 1] - offsets[k];
+        if (M < 1) {
+            index[k] = -1;
+            if (alpha0) alpha0[k] = 0.0f;
+            if (trials) trials[k] = 0;
+            continue;
+        }
+        index[k] = select_uniform_one(alpha + offsets[k], 1, M, NULL, 0u, (uint32_t)k,
+                                      seed, step, 0u, t_max,
+                                      alpha0 ? alpha0 + k : NULL,
+                                      trials ? trials + k : NULL);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* AR with an integer proposal Q (acceptance probability               */
+/* alpha_j / (c+ * Q_j)); the candidate is drawn from Q by the inverse  */
+/* transform of its exact integer prefix sums.                          */
+/* -4: the proposal is unusable (sum Q >= 2^32, or Q_j = 0 where        */
+/* alpha_j > 0).                                                         */
+/* ------------------------------------------------------------------ */
+static int32_t select_proposal_one(const float *a, const uint32_t *q, int64_t M,
+                                   uint32_t k, uint64_t seed, uint64_t step,
+                                   uint32_t t_max, uint32_t *trials, uint32_t *prefix)
+{
+    float amax;
+    if (trials) *trials = 0;
+    if (scan_max(a, 1, M, &amax) != 0) return -2;
+    if (amax == 0.0f) return -1;
+    uint64_t SQ = 0;
+    double c = 0.0;
+    for (int64_t j = 0; j < M; ++j) {
+        if (a[j] > 0.0f && q[j] == 0u) return -4;
+        SQ += q[j];
+        prefix[j] = (uint32_t)SQ;
+        if (a[j] > 0.0f) {
+            double r = (double)a[j] / (double)q[j];
+            if (r > c) c = r;
+        }
+    }
+    if (SQ >= ((uint64_t)1 << 32)) return -4;
+    /* c+ >= alpha_j / Q_j for every j, so no acceptance probability saturates */
+    double cplus = nextafter(c, INFINITY);
+    uint32_t sq = (uint32_t)SQ;
+    uint32_t lemire_floor = (0u - sq) % sq;
+    for (uint32_t t = 0; t < t_max; ++t) {
+        uint32_t w[4];
+        draw(seed, t, k, step, 1u, w);
+        uint64_t m = (uint64_t)w[0] * (uint64_t)sq;
+        if ((uint32_t)m < lemire_floor) continue;
+        uint32_t V = (uint32_t)(m >> 32);
+        /* least j with prefix[j] > V: binary search over the prefix sums */
+        int64_t lo = 0, hi = M - 1;
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (prefix[mid] > V) hi = mid; else lo = mid + 1;
+        }
+        int64_t j = lo;
+        double u = grid_u(w[1], w[2]);
+        double uc = u * cplus;
+        if (uc * (double)q[j] < (double)a[j]) {
+            if (trials) *trials = t + 1;
+            return (int32_t)j;
+        }
+    }
+    int L = ceil_log2(M);
+    int E;
+    frexpf(amax, &E);
+    int shift = 63 - L - E;
+    uint64_t S = fixed_sum(a, 1, M, shift);
+    uint32_t w[4];
+    draw(seed, FALLBACK_WORD, k, step, 1u, w);
+    uint64_t V = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    if (trials) *trials = t_max + 1;
+    return fallback_pick(a, 1, M, shift, S, V);
+}
+
+/* alpha[k*lda + j], Q[k*ldq + j]. */
+int orc_select_proposal(const float *alpha, const uint32_t *Q, int64_t M, int64_t K,
+                        int64_t lda, int64_t ldq, uint64_t seed, uint64_t step,
+                        uint32_t t_max, int32_t *index, uint32_t *trials, int threads)
+{
+    if (M < 1 || K < 0) return -1;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel if (threads != 1)
+#endif
+    {
+        uint32_t *prefix = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)M);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t k = 0; k < K; ++k) {
+            index[k] = select_proposal_one(alpha + k * lda, Q + k * ldq, M, (uint32_t)k,
+                                           seed, step, t_max,
+                                           trials ? trials + k : NULL, prefix);
+        }
+        free(prefix);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Mass-action propensities and the SSA jump chain (state sequence of   */
+/* the direct method; the holding times do not change the sequence).    */
+/* ------------------------------------------------------------------ */
+static float mass_action(const int32_t *x, int32_t r0, int32_t r1, float rate)
+{
+    int64_t h;
+    if (r1 < 0)        h = x[r0];
+    else if (r1 == r0) h = (int64_t)x[r0] * (x[r0] - 1) / 2;
+    else               h = (int64_t)x[r0] * x[r1];
+    return rate * (float)h;
+}
+
+/* alpha[r*M + j] for states X[r*N + i]. */
+void orc_propensities(const int32_t *X, int64_t R, int64_t N, int64_t M,
+                      const int32_t *r0, const int32_t *r1, const float *rate,
+                      float *alpha)
+{
+    (void)N;
+    for (int64_t r = 0; r < R; ++r)
+        for (int64_t j = 0; j < M; ++j)
+            alpha[r * M + j] = mass_action(X + r * N, r0[j], r1[j], rate[j]);
+}
+
+/* Run `steps` jump-chain steps for R realizations in place on X[r*N + i].
+ * Step i of realization r selects with uniform AR (tag 2, instance r,
+ * step step0 + i); a selection < 0 (nothing can fire) leaves the state.
+ * When rec_X is non-NULL, the state before each step i >= rec_from is
+ * written to rec_X[((i - rec_from) * R + r) * N + ...]. */
+int orc_ssa_chain(int32_t *X, int64_t R, int64_t N, int64_t M,
+                  const int32_t *r0, const int32_t *r1, const int32_t *p0,
+                  const int32_t *p1, const float *rate, uint64_t seed, uint64_t step0,
+                  int64_t steps, uint32_t t_max, int64_t rec_from, int32_t *rec_X,
+                  int32_t *fired, int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel if (threads != 1)
+#endif
+    {
+        float *a = (float *)malloc(sizeof(float) * (size_t)M);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t r = 0; r < R; ++r) {
+            int32_t *x = X + r * N;
+            for (int64_t i = 0; i < steps; ++i) {
+                if (rec_X && i >= rec_from)
+                    memcpy(rec_X + ((i - rec_from) * R + r) * N, x, sizeof(int32_t) * (size_t)N);
+                for (int64_t j = 0; j < M; ++j)
+                    a[j] = mass_action(x, r0[j], r1[j], rate[j]);
+                int32_t j = select_uniform_one(a, 1, M, NULL, 0u, (uint32_t)r, seed,
+                                               step0 + (uint64_t)i, 2u, t_max, NULL, NULL);
+                if (fired) fired[i * R + r] = j;
+                if (j < 0) continue;
+                x[r0[j]] -= 1;
+                if (r1[j] >= 0) x[r1[j]] -= 1;
+                x[p0[j]] += 1;
+                if (p1[j] >= 0) x[p1[j]] += 1;
+            }
+        }
+        free(a);
+    }
+    return 0;
+}
