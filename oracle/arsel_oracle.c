@@ -29,10 +29,13 @@
  *    update X <- X + v_j used by the jump-chain data generator.
  *
  * Readings where the paper is silent are listed in the design notes; the
- * ones that fix arithmetic here: u lives on the 53-bit grid {0, 2^-53, ...,
- * 1 - 2^-53} and the product u*alpha_max is one binary64 multiply (a 24-bit
- * float grid would over-weight reactions with alpha_j < 2^-24 alpha_max);
- * acceptance is strict (u*alpha_max < alpha_j); candidates are
+ * ones that fix arithmetic here: one Philox block b yields two trials,
+ * t = 2b (words 0, 1) and t = 2b+1 (words 2, 3); in each trial the first
+ * word picks the candidate and the second is u on the 32-bit grid
+ * {0, 2^-32, ..., 1 - 2^-32}; the product u*alpha_max is one binary64
+ * multiply (a 24-bit float grid would over-weight reactions with
+ * alpha_j < 2^-24 alpha_max); acceptance is strict (u*alpha_max < alpha_j);
+ * candidates are
  * exactly uniform (Lemire multiply-shift with its rejection folded into the
  * trial); indexes are 0-based; -1 means every propensity is zero and -2 an
  * invalid (NaN, negative, +inf) propensity.
@@ -78,7 +81,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 /* Counter layout of one random draw: (word0, instance, step lo, step hi ^ tag<<28).
  * Tags: 0 uniform select, 1 proposal select, 2 SSA data generation.
- * word0 is the trial index; 0xFFFFFFFF is reserved for the fallback draw. */
+ * word0 is the trial block t/2; 0xFFFFFFFF is reserved for the fallback draw. */
 #define FALLBACK_WORD 0xFFFFFFFFu
 
 static void draw(uint64_t seed, uint32_t word0, uint32_t inst, uint64_t step,
@@ -90,11 +93,20 @@ static void draw(uint64_t seed, uint32_t word0, uint32_t inst, uint64_t step,
     orc_philox4x32_10(ctr, key, out);
 }
 
-/* u on the 53-bit grid {0, 2^-53, ..., 1 - 2^-53}: 32 bits of w1 above the
- * top 21 bits of w2.  Both terms and their sum are exact in binary64. */
-static double grid_u(uint32_t w1, uint32_t w2)
+/* u on the 32-bit grid {0, 2^-32, ..., 1 - 2^-32}, exact in binary64. */
+static double grid_u(uint32_t w)
 {
-    return (double)w1 * 0x1p-32 + (double)(w2 >> 11) * 0x1p-53;
+    return (double)w * 0x1p-32;
+}
+
+/* Trial t: candidate word and u word. */
+static void trial_words(uint64_t seed, uint32_t t, uint32_t inst, uint64_t step,
+                        uint32_t tag, uint32_t *cand, uint32_t *uw)
+{
+    uint32_t w[4];
+    draw(seed, t >> 1, inst, step, tag, w);
+    *cand = w[2 * (t & 1)];
+    *uw = w[2 * (t & 1) + 1];
 }
 
 /* L = ceil(log2 M), 0 for M = 1. */
@@ -210,12 +222,12 @@ static int32_t select_uniform_one(const float *a, int64_t stride, int64_t M,
     /* The sequential rule: trials t = 0, 1, ...; the first accepted wins. */
     uint32_t lemire_floor = (uint32_t)(0u - (uint32_t)M) % (uint32_t)M; /* 2^32 mod M */
     for (uint32_t t = 0; t < t_max; ++t) {
-        uint32_t w[4];
-        draw(seed, t, k, step, tag, w);
-        uint64_t m = (uint64_t)w[0] * (uint64_t)M;
+        uint32_t cw, uw;
+        trial_words(seed, t, k, step, tag, &cw, &uw);
+        uint64_t m = (uint64_t)cw * (uint64_t)M;
         if ((uint32_t)m < lemire_floor) continue;  /* candidate draw rejected */
         int64_t j = (int64_t)(m >> 32);
-        double u = grid_u(w[1], w[2]);
+        double u = grid_u(uw);
         if (u * (double)env < (double)a[j * stride]) {
             if (trials) *trials = t + 1;
             return (int32_t)j;
@@ -321,9 +333,9 @@ static int32_t select_proposal_one(const float *a, const uint32_t *q, int64_t M,
     uint32_t sq = (uint32_t)SQ;
     uint32_t lemire_floor = (0u - sq) % sq;
     for (uint32_t t = 0; t < t_max; ++t) {
-        uint32_t w[4];
-        draw(seed, t, k, step, 1u, w);
-        uint64_t m = (uint64_t)w[0] * (uint64_t)sq;
+        uint32_t cw, uw;
+        trial_words(seed, t, k, step, 1u, &cw, &uw);
+        uint64_t m = (uint64_t)cw * (uint64_t)sq;
         if ((uint32_t)m < lemire_floor) continue;
         uint32_t V = (uint32_t)(m >> 32);
         /* least j with prefix[j] > V: binary search over the prefix sums */
@@ -333,7 +345,7 @@ static int32_t select_proposal_one(const float *a, const uint32_t *q, int64_t M,
             if (prefix[mid] > V) hi = mid; else lo = mid + 1;
         }
         int64_t j = lo;
-        double u = grid_u(w[1], w[2]);
+        double u = grid_u(uw);
         double uc = u * cplus;
         if (uc * (double)q[j] < (double)a[j]) {
             if (trials) *trials = t + 1;

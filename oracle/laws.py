@@ -5,20 +5,20 @@ code through chi-square tests and exact identities.
 
 Uniform AR (the sequential rule of the paper's section "A GPU
 acceptance-rejection algorithm (GPU/AR) for SSA"), with the readings used by
-the oracle: one trial draws a 32-bit word w0, maps it to a candidate by
+the oracle: one trial takes a 32-bit candidate word, maps it to a candidate by
 Lemire's multiply-shift (rejecting the 2^32 mod M lowest remainders, so the
 candidate is exactly uniform), and accepts when fl64(u * env) < alpha_j for u
-on the 53-bit grid.  Per candidate j the number of grid points that accept is
+on the 32-bit grid.  Per candidate j the number of grid points that accept is
 
-    A_j = #{ v in [0, 2^53) : fl64(v 2^-53 * env) < alpha_j },
+    A_j = #{ v in [0, 2^32) : fl64(v 2^-32 * env) < alpha_j },
 
 a monotone predicate in v, so it is found by binary search.  A trial accepts
-(and picks j) with probability (1 - eps) / M * A_j / 2^53, eps = (2^32 mod M)
+(and picks j) with probability (1 - eps) / M * A_j / 2^32, eps = (2^32 mod M)
 / 2^32.  After t_max rejected trials the inverse transform of the section
 "The Stochastic Simulation Algorithm" picks j with probability F_j / S in
 exact fixed point.  So
 
-    P(j) = (1 - (1-a)^T) A_j / sum A + (1-a)^T F_j / S,   a = (1-eps) sum A / (M 2^53).
+    P(j) = (1 - (1-a)^T) A_j / sum A + (1-a)^T F_j / S,   a = (1-eps) sum A / (M 2^32).
 """
 from __future__ import annotations
 
@@ -34,12 +34,12 @@ def ceil_log2(M: int) -> int:
     return L
 
 
-GRID_BITS = 53
+GRID_BITS = 32
 GRID = 1 << GRID_BITS
 
 
 def _count_below(pred) -> np.ndarray:
-    """Least v in [0, 2^53] where the monotone predicate pred(v) is false."""
+    """Least v in [0, GRID] where the monotone predicate pred(v) is false."""
     # pred takes an int64 array of v values and returns a bool array
     probe = pred(np.zeros(1, dtype=np.int64))
     shape = probe.shape
@@ -54,7 +54,7 @@ def _count_below(pred) -> np.ndarray:
 
 
 def accept_counts(alpha: np.ndarray, env: float) -> np.ndarray:
-    """A_j for every j (int64): grid points v with fl64(v 2^-53 env) < alpha_j."""
+    """A_j for every j (int64): grid points v with fl64(v 2^-32 env) < alpha_j."""
     a = np.asarray(alpha, dtype=np.float32).astype(np.float64)
     env = float(np.float32(env))
 
@@ -66,7 +66,7 @@ def accept_counts(alpha: np.ndarray, env: float) -> np.ndarray:
 
 
 def accept_counts_proposal(alpha: np.ndarray, Q: np.ndarray, cplus: float) -> np.ndarray:
-    """A_j = #{v : fl64(fl64(v 2^-53 c+) Q_j) < alpha_j}."""
+    """A_j = #{v : fl64(fl64(v 2^-32 c+) Q_j) < alpha_j}."""
     a = np.asarray(alpha, dtype=np.float32).astype(np.float64)
     qd = np.asarray(Q, dtype=np.uint32).astype(np.float64)
     c = float(cplus)

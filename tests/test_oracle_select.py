@@ -1,7 +1,7 @@
 """Pins of the oracle's uniform acceptance-rejection selector.
 
 What fixes the answers here is not the oracle itself:
-  * the exact output law (oracle/laws.py, an enumeration over the 53-bit u
+  * the exact output law (oracle/laws.py, an enumeration over the 32-bit u
     grid) and chi-square tests against it and against alpha_j / alpha_0
     (the SSA's selection law, section "The Stochastic Simulation Algorithm");
   * an independent numpy inverse transform for the fallback;
@@ -17,13 +17,20 @@ from oracle import laws
 from paper_1404_0027_amd import workloads
 
 
+def _trial_words(seed, t, k, step, tag=0):
+    """Trial t uses Philox block t // 2: words (0, 1) for even t, (2, 3) for odd."""
+    w = oracle.draw(seed, t >> 1, k, step, tag)
+    h = t & 1
+    return int(w[2 * h]), int(w[2 * h + 1])
+
+
 def _lemire_reference(seed, k, step, M, t_max, tag=0):
     """Candidate of the first trial whose Lemire draw is not rejected, by
     Python integer arithmetic on Philox words."""
     thr = (1 << 32) % M
     for t in range(t_max):
-        w = oracle.draw(seed, t, k, step, tag)
-        m = int(w[0]) * M
+        cw, _ = _trial_words(seed, t, k, step, tag)
+        m = cw * M
         if (m & 0xFFFFFFFF) >= thr:
             return m >> 32, t + 1
     return None, None
@@ -43,7 +50,7 @@ def test_lemire_fold_rule_exhaustive_16bit():
 
 
 def test_all_equal_is_first_unrejected_candidate():
-    """With every alpha_j equal, fl64((1-2^-53) a) < a, so every trial that
+    """With every alpha_j equal, fl64((1-2^-32) a) < a, so every trial that
     survives the candidate draw accepts."""
     M, K = 1029, 300
     a = np.full(M, 3.5, dtype=np.float32)
@@ -68,10 +75,9 @@ def test_lemire_rejections_are_skipped():
 
 def test_trial_sequence_brute_force():
     """Replay the trial sequence with Python integers and exact rationals:
-    candidate j = floor(w0 M / 2^32) unless Lemire rejects; u = (w1 2^21 +
-    (w2 >> 11)) / 2^53; accept iff u * alpha_max < alpha_j, decided exactly
-    (the binary64 product only rounds where u * alpha_max is within an ulp of
-    alpha_j, which these inputs never hit)."""
+    candidate j = floor(c M / 2^32) unless Lemire rejects; u = v / 2^32;
+    accept iff u * alpha_max < alpha_j, decided exactly (the binary64 product
+    of a 32-bit u and a 24-bit alpha_max is exact)."""
     from fractions import Fraction
 
     a = np.array([0.5, 0.0, 2.0, 1.25, 0.03125, 3.0, 0.75, 1.5], np.float32)
@@ -80,12 +86,12 @@ def test_trial_sequence_brute_force():
     amax = Fraction(float(a.max()))
     for k in range(K):
         for t in range(4096):
-            w = [int(x) for x in oracle.draw(123, t, k, 77, 0)]
-            m = w[0] * M
+            cw, uw = _trial_words(123, t, k, 77, 0)
+            m = cw * M
             if (m & 0xFFFFFFFF) < (1 << 32) % M:
                 continue
             j = m >> 32
-            u = Fraction((w[1] << 21) | (w[2] >> 11), 1 << 53)
+            u = Fraction(uw, 1 << 32)
             if u * amax < Fraction(float(a[j])):
                 break
         assert idx[k] == j and tr[k] == t + 1, k
