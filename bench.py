@@ -1,0 +1,180 @@
+"""Benchmark: batched acceptance-rejection next-reaction selection on one MI355X.
+
+Workload: R = 4096 realizations, each with its own FP32 propensity vector of
+M = 1029 reactions (lognormal(0,2), 30% set exactly to zero), stored SoA
+(alpha[j*4096 + k]); one selection per realization per step; 32 distinct
+propensity batches (540 MB, more than the 256 MB Infinity Cache) rotated
+across steps; Philox4x32-10 seed 1, step counter = step index.  The K timed
+steps are captured in one HIP graph and replayed once between HIP events.
+
+Prints one JSON line: selections/s, the roofline of the selection kernel
+(algorithmic bytes: 4 B per propensity + 4 B per index), the per-trial
+acceptance of uniform AR on this workload, and the CPU oracle timed on a
+bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M, R, NBUF, SEED = 1029, 4096, 32, 1
+BYTES_PER_SELECTION = 4 * M + 4
+HBM_PEAK_GBS = 8000.0
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    from paper_1404_0027_amd.profiling import source_hash
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(buf_host, threads: int, budget_s: float = 8.0):
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.select_uniform(buf_host[0], M, R, R, oracle.SOA, seed=SEED, step=0, threads=threads,
+                          want_alpha0=False, want_trials=False)
+    one = time.perf_counter() - t0
+    steps = max(1, min(NBUF * 8, int(budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    for s in range(steps):
+        oracle.select_uniform(buf_host[s % NBUF], M, R, R, oracle.SOA, seed=SEED, step=s,
+                              threads=threads, want_alpha0=False, want_trials=False)
+    dt = time.perf_counter() - t0
+    return {"value": steps * R / dt, "unit": "selections/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} steps x {R} realizations of the same workload (M={M} SoA), "
+                      f"sequential AR per instance, OpenMP over instances"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tile", type=int, default=0, help="dense tile override (results unchanged)")
+    ap.add_argument("--waves", type=int, default=0, help="dense waves override (results unchanged)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(instances are independent: the multi-GPU design shards realizations, "
+              f"see the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1404_0027_amd import arsel, workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print(f"[bench] generating {NBUF} x {M} x {R} propensities", file=sys.stderr, flush=True)
+    host = workloads.lognormal_soa(M=M, K=R, seed=2, buffers=NBUF)
+    bufs = torch.from_numpy(host).to(dev)
+    index = torch.empty(R, dtype=torch.int32, device=dev)
+    arsel.context(0)
+    if args.tile or args.waves:
+        arsel.set_dense_config(args.tile or 16, args.waves or 16)
+
+    def launch(s: int):
+        b = bufs[s % NBUF]
+        arsel.select(b, M, R, R, arsel.SOA, seed=SEED, step=s, index=index)
+
+    for s in range(args.warmup):
+        launch(s)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup {args.warmup} steps done; capturing {args.steps}", file=sys.stderr,
+          flush=True)
+
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(g, stream=cap, capture_error_mode="relaxed"):
+            for s in range(args.steps):
+                launch(s)
+    torch.cuda.synchronize()
+
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    g.replay()
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    sel_per_s = args.steps * R / (ms * 1e-3)
+    avg_launch_s = ms * 1e-3 / args.steps
+    print(f"[bench] {args.steps} steps in {ms:.3f} ms ({avg_launch_s*1e6:.2f} us/step)",
+          file=sys.stderr, flush=True)
+
+    # parity of the last timed step against the oracle
+    import oracle
+
+    last = args.steps - 1
+    got = index.cpu().numpy()
+    ref = oracle.select_uniform(host[last % NBUF], M, R, R, oracle.SOA, seed=SEED, step=last,
+                                threads=min(16, os.cpu_count() or 1), want_alpha0=False,
+                                want_trials=False)[0]
+    parity = "ok" if np.array_equal(got, ref) else f"MISMATCH ({int((got != ref).sum())} of {R})"
+
+    # acceptance of uniform AR on this workload (trials of 32 steps)
+    trials = torch.empty(R, dtype=torch.int32, device=dev)
+    tsum = nfb = nsel = 0
+    for s in range(32):
+        arsel.select(bufs[s], M, R, R, arsel.SOA, seed=SEED, step=s, index=index, trials=trials)
+        t = trials.cpu().numpy().view(np.uint32).astype(np.int64)
+        ok = t <= 4096
+        tsum += int(t[ok].sum()) + 4096 * int((~ok).sum())
+        nfb += int((~ok).sum())
+        nsel += int((t > 0).sum())
+    acceptance = {"uniform_per_trial": nsel / tsum if tsum else None,
+                  "uniform_mean_trials": tsum / max(nsel, 1),
+                  "fallback_fraction": nfb / max(nsel, 1),
+                  "learned_per_trial": None}
+
+    bytes_per_launch = R * BYTES_PER_SELECTION
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = load_traffic("select_tile")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(host, threads=min(16, os.cpu_count() or 1))
+
+    out = {
+        "metric": "next-reaction selections/sec at M=1029 (batched) + AR acceptance rate vs learned q",
+        "value": round(sel_per_s, 1), "unit": "selections/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched uniform AR: R=4096 realizations x M=1029 reactions, SoA, "
+                               "lognormal(0,2) with 30% zeros, 32 rotating batches, one "
+                               "selection per realization per step, HIP graph of all steps",
+                   "R": R, "M": M, "layout": "SoA", "buffers": NBUF, "seed": SEED},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "acceptance": acceptance,
+        "parity_last_step": parity,
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if parity == "ok" else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,149 @@
+/*
+ * arsel -- batched acceptance-rejection selection of the next reaction to
+ * occur in Gillespie's SSA, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Neri & Mestivier, arXiv:1404.0027.  For each of K propensity
+ * vectors alpha[0..M) the library returns one reaction index j with
+ * probability alpha_j / alpha_0 (alpha_0 = sum_j alpha_j), the selection law
+ * of the direct method (section "The Stochastic Simulation Algorithm"),
+ * reached by the acceptance-rejection rule of section "A GPU
+ * acceptance-rejection algorithm (GPU/AR) for SSA": draw j uniformly and u
+ * uniformly in [0,1), accept when u * alpha_max < alpha_j, else draw again.
+ *
+ * Random stream.  Counter-based Philox4x32-10 keyed by the 64-bit seed.
+ * Trial t of instance k at step s uses the block with counter
+ * (t/2, k, s mod 2^32, (s >> 32) ^ (tag << 28)); even t takes words (0,1),
+ * odd t words (2,3).  The first word of a trial gives the candidate by
+ * Lemire's multiply-shift (the 2^32 mod M lowest products are rejected so
+ * candidates are exactly uniform), the second gives u = w * 2^-32; the test
+ * u * alpha_max < alpha_j is made in binary64.  The answer is the accepted
+ * trial with the least t, so it does not depend on how many trials the GPU
+ * runs at once.  When t_max trials all reject, the inverse transform of
+ * the direct method picks j in exact 64-bit fixed point with the block
+ * (0xFFFFFFFF, k, ...): F_j = floor(alpha_j 2^(63-L-E)), L = ceil(log2 M),
+ * 2^(E-1) <= alpha_max < 2^E; V = word0 | word1 << 32; j is the least index
+ * whose inclusive prefix of F exceeds floor(V * sum F / 2^64).
+ * Tags: 0 uniform selection, 1 proposal selection, 2 SSA data generation.
+ *
+ * Conventions for every entry point.
+ *  - Array pointers are DEVICE pointers owned by the caller; the library never
+ *    frees them and keeps none of them after the call returns.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *    null stream); no call synchronises the device.
+ *  - A negative return value is an argument error detected on the host
+ *    before anything is launched, or a launch failure (ARSEL_ERR_HIP).
+ *  - Per-instance outcomes are reported in `index`: >= 0 the selected
+ *    reaction; -1 every propensity is zero (nothing can fire; the paper
+ *    returns an out-of-range index in that case); -2 a propensity is NaN,
+ *    negative or +inf; -3 a supplied bound is below the true maximum (only
+ *    with ARSEL_DEBUG_CHECK_BOUND); -4 an unusable proposal.
+ *  - One context per host thread; calls on one context are not thread-safe.
+ */
+#ifndef ARSEL_H
+#define ARSEL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct arsel_ctx arsel_ctx;
+
+enum {
+    ARSEL_OK = 0,
+    ARSEL_ERR_NULL = -1,        /* a required pointer is NULL */
+    ARSEL_ERR_SIZE = -2,        /* M < 1, K < 0, or a size beyond the 32-bit index range */
+    ARSEL_ERR_LAYOUT = -3,      /* layout is neither ARSEL_AOS nor ARSEL_SOA */
+    ARSEL_ERR_LD = -4,          /* leading dimension too small for the layout */
+    ARSEL_ERR_HIP = -5,         /* a HIP call or kernel launch failed */
+    ARSEL_ERR_DEVICE = -6,      /* bad device id, or the device is not gfx950 */
+    ARSEL_ERR_ALLOC = -7,       /* host or device allocation failed */
+    ARSEL_ERR_ARG = -8          /* another invalid argument (named by arsel_strerror) */
+};
+
+enum { ARSEL_AOS = 0, ARSEL_SOA = 1 };
+
+/* flags */
+#define ARSEL_DEBUG_CHECK_BOUND 1u   /* scan alpha even with a supplied bound; -3 if bound < max */
+
+/* Create a context on HIP device `device` (makes it current while creating).
+ * The context holds device properties, a small device scratch area and the
+ * schedule table used by arsel_select_ragged.  Returns ARSEL_OK or an error. */
+int arsel_create(arsel_ctx **out, int device);
+
+/* Free the context and its device scratch.  NULL is accepted. */
+int arsel_destroy(arsel_ctx *ctx);
+
+/* Text for an error code (static storage). */
+const char *arsel_strerror(int code);
+
+/*
+ * Dense batch: K instances with M reactions each (section "Results /
+ * Implementation": propensities of realization k stored as D[k*M + j]).
+ *   layout ARSEL_AOS: alpha[k*ld + j]; ld == 0 broadcasts one vector to all K
+ *                     instances; otherwise ld >= M.
+ *   layout ARSEL_SOA: alpha[j*ld + k], ld >= K (coalesced across instances).
+ *   bound:   NULL -> alpha_max is computed per instance (exact maximum);
+ *            else K per-instance bounds B_k >= max_j alpha_j used in place of
+ *            alpha_max (any such bound keeps the law exact; it only lowers
+ *            the acceptance rate).  B_k == 0 reports -1; NaN, negative or +inf
+ *            reports -2.
+ *   seed, step: Philox key and step counter (advance step between calls).
+ *   t_max:   trial budget before the inverse-transform fallback (0 forces the
+ *            fallback; 4096 is a good default).
+ *   index:   [K] int32 output.  alpha0: NULL or [K] float output, the
+ *            fixed-point alpha_0 rounded to float.  trials: NULL or [K]
+ *            uint32 output, the accepted trial index + 1, t_max + 1 after the
+ *            fallback, 0 for -1/-2/-3.
+ * Results are bit-identical to the sequential rule described above.
+ */
+int arsel_select(arsel_ctx *ctx, const float *alpha, int32_t M, int32_t K, int64_t ld,
+                 int layout, const float *bound, uint64_t seed, uint64_t step,
+                 uint32_t t_max, uint32_t flags, int32_t *index, float *alpha0,
+                 uint32_t *trials, void *stream);
+
+/* Dense-path schedule: at most `tile` instances per workgroup tile (1..64)
+ * and `waves` wavefronts per workgroup (4, 8 or 16).  Results never change. */
+int arsel_set_dense_config(arsel_ctx *ctx, int32_t tile, int32_t waves);
+
+/*
+ * Uneven batch in one persistent launch: instance k has
+ * M_k = offsets[k+1] - offsets[k] reactions at alpha[offsets[k] ..] (AoS).
+ * offsets is a DEVICE array of K+1 int64; host_sizes is NULL or a HOST array
+ * of the K sizes, used only to order the work longest-first and to choose the
+ * per-instance schedule (wave or whole workgroup, LDS staging); when NULL the
+ * work is taken in index order with one schedule.  M_k == 0 reports -1.
+ * Results are bit-identical to arsel_select on each instance with instance
+ * id k, whatever the schedule.
+ */
+int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offsets,
+                        int32_t K, const int64_t *host_sizes, uint64_t seed, uint64_t step,
+                        uint32_t t_max, int32_t *index, float *alpha0, uint32_t *trials,
+                        void *stream);
+
+/*
+ * Schedule of arsel_select_ragged (chosen by the autotuner).
+ *   wave_max_m:  instances with M <= wave_max_m are run by one wavefront each;
+ *                larger ones by a whole workgroup.
+ *   block_waves: wavefronts per workgroup (1, 2, 4, 8 or 16).
+ *   lds_max_m:   instances with M <= lds_max_m are staged in LDS; larger ones
+ *                are gathered from global memory.
+ *   blocks_per_cu: persistent workgroups launched per compute unit.
+ * The schedule never changes results.
+ */
+typedef struct {
+    int32_t wave_max_m;
+    int32_t block_waves;
+    int32_t lds_max_m;
+    int32_t blocks_per_cu;
+} arsel_schedule;
+
+int arsel_get_schedule(arsel_ctx *ctx, arsel_schedule *out);
+int arsel_set_schedule(arsel_ctx *ctx, const arsel_schedule *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARSEL_H */

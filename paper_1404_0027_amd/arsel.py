@@ -1,0 +1,173 @@
+"""Python binding of libarsel.so (ctypes; argument marshalling only).
+
+Every step of the selection runs in the library's HIP kernels.  PyTorch is
+used for device memory and streams: tensors in, tensors out, launched on the
+current torch stream.  If the library is missing this module raises; there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libarsel.so")
+
+AOS, SOA = 0, 1
+DEBUG_CHECK_BOUND = 1
+TAG_UNIFORM, TAG_PROPOSAL, TAG_SSA = 0, 1, 2
+
+
+class ArselError(RuntimeError):
+    pass
+
+
+_lib = None
+_lock = threading.Lock()
+_ctx: dict[int, ctypes.c_void_p] = {}
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ArselError(f"{LIB_PATH} is not built; run `python -m paper_1404_0027_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                 ctypes.c_uint32, ctypes.c_uint64)
+        L.arsel_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+        L.arsel_create.restype = ctypes.c_int
+        L.arsel_destroy.argtypes = [P]
+        L.arsel_destroy.restype = ctypes.c_int
+        L.arsel_strerror.argtypes = [ctypes.c_int]
+        L.arsel_strerror.restype = ctypes.c_char_p
+        L.arsel_select.argtypes = [P, P, i32, i32, i64, ctypes.c_int, P, u64, u64, u32, u32,
+                                   P, P, P, P]
+        L.arsel_select.restype = ctypes.c_int
+        for name, argtypes in _EXTRA_SIGNATURES.items():
+            fn = getattr(L, name, None)
+            if fn is not None:
+                fn.argtypes = argtypes
+                fn.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("wave_max_m", ctypes.c_int32), ("block_waves", ctypes.c_int32),
+                ("lds_max_m", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_EXTRA_SIGNATURES = {
+    "arsel_select_ragged": [_P, _P, _P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64,
+                            ctypes.c_uint32, _P, _P, _P, _P],
+    "arsel_get_schedule": [_P, ctypes.POINTER(Schedule)],
+    "arsel_set_schedule": [_P, ctypes.POINTER(Schedule)],
+    "arsel_set_dense_config": [_P, ctypes.c_int32, ctypes.c_int32],
+}
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        msg = lib().arsel_strerror(rc).decode()
+        raise ArselError(f"{what} failed ({rc}): {msg}")
+
+
+def context(device: int | torch.device | None = None) -> ctypes.c_void_p:
+    """The library context of a device (created once per process)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    if isinstance(device, torch.device):
+        device = device.index if device.index is not None else torch.cuda.current_device()
+    with _lock:
+        c = _ctx.get(device)
+        if c is None:
+            c = ctypes.c_void_p()
+            _check(lib().arsel_create(ctypes.byref(c), device), "arsel_create")
+            _ctx[device] = c
+    return c
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, numel: int, name: str, device) -> None:
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype:
+        raise ArselError(f"{name} must be a {dtype} tensor")
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ArselError(f"{name} must live on the same GPU")
+    if not t.is_contiguous():
+        raise ArselError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ArselError(f"{name} holds {t.numel()} elements, {numel} needed")
+
+
+def select(alpha: torch.Tensor, M: int, K: int, ld: int, layout: int = AOS, *, seed: int,
+           step: int = 0, t_max: int = 4096, bound: torch.Tensor | None = None, flags: int = 0,
+           want_alpha0: bool = False, want_trials: bool = False,
+           index: torch.Tensor | None = None, alpha0: torch.Tensor | None = None,
+           trials: torch.Tensor | None = None):
+    """K selections from a dense batch (see arsel_select in include/arsel.h).
+
+    alpha: float32 CUDA tensor; AoS element (k, j) at k*ld + j (ld = 0: one
+    vector for all), SoA element (k, j) at j*ld + k.  Returns
+    (index int32 [K], alpha0 float32 [K] or None, trials int32 [K] or None);
+    trials hold uint32 bit patterns.
+    """
+    dev = alpha.device
+    if layout == AOS:
+        need = M if ld == 0 else (K - 1) * ld + M if K > 0 else 0
+    else:
+        need = (M - 1) * ld + K if K > 0 else 0
+    _need(alpha, torch.float32, need, "alpha", None)
+    if index is None:
+        index = torch.empty(K, dtype=torch.int32, device=dev)
+    _need(index, torch.int32, K, "index", dev)
+    if want_alpha0 and alpha0 is None:
+        alpha0 = torch.empty(K, dtype=torch.float32, device=dev)
+    if alpha0 is not None:
+        _need(alpha0, torch.float32, K, "alpha0", dev)
+    if want_trials and trials is None:
+        trials = torch.empty(K, dtype=torch.int32, device=dev)
+    if trials is not None:
+        _need(trials, torch.int32, K, "trials", dev)
+    if bound is not None:
+        _need(bound, torch.float32, K, "bound", dev)
+    rc = lib().arsel_select(context(dev), _ptr(alpha), M, K, ld, layout, _ptr(bound),
+                            seed & (2**64 - 1), step & (2**64 - 1), t_max, flags, _ptr(index),
+                            _ptr(alpha0), _ptr(trials), _stream(dev))
+    _check(rc, "arsel_select")
+    return index, alpha0, trials
+
+
+def select_raw(ctx, alpha_ptr: int, M: int, K: int, ld: int, layout: int, bound_ptr, seed: int,
+               step: int, t_max: int, flags: int, index_ptr: int, alpha0_ptr, trials_ptr,
+               stream_handle: int) -> int:
+    """Unchecked call with raw device pointers (for timing loops and tests of
+    the host-side argument checks).  Returns the library's status code."""
+    return lib().arsel_select(ctx, alpha_ptr, M, K, ld, layout, bound_ptr, seed, step, t_max,
+                              flags, index_ptr, alpha0_ptr, trials_ptr, stream_handle)
+
+
+def set_dense_config(tile: int, waves: int, device=None) -> None:
+    """Instances per dense tile and wavefronts per workgroup (results unchanged)."""
+    _check(lib().arsel_set_dense_config(context(device), tile, waves), "arsel_set_dense_config")
+
+
+def get_schedule(device=None) -> Schedule:
+    s = Schedule()
+    _check(lib().arsel_get_schedule(context(device), ctypes.byref(s)), "arsel_get_schedule")
+    return s
+
+
+def set_schedule(s: Schedule, device=None) -> None:
+    _check(lib().arsel_set_schedule(context(device), ctypes.byref(s)), "arsel_set_schedule")

@@ -1,0 +1,34 @@
+// Host-side context shared by the entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "../../include/arsel.h"
+
+struct arsel_ctx {
+    int device;
+    int num_cu;
+    size_t lds_per_block;     // device limit on LDS per workgroup (bytes)
+    size_t tile_lds_bytes;    // LDS budget of one dense tile
+    int dense_tile;           // instances per dense tile (upper bound)
+    int dense_waves;          // wavefronts per dense workgroup (4, 8, 16)
+    arsel_schedule sched;     // ragged schedule
+    uint32_t *queue;          // device work counter of the persistent ragged kernel
+    int32_t *order;           // device instance order (longest first), grown on demand
+    int32_t order_cap;
+};
+
+namespace arsel {
+
+inline int ctx_activate(arsel_ctx *ctx)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return ARSEL_ERR_HIP;
+    if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess) return ARSEL_ERR_DEVICE;
+    return ARSEL_OK;
+}
+
+}  // namespace arsel

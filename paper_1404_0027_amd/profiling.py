@@ -1,0 +1,123 @@
+"""Profiling helpers: counter calibration and rocprofv3 summaries.
+
+    python -m paper_1404_0027_amd.profiling copy
+        Runs a plain device copy of known size (64 MiB read, 64 MiB written,
+        20 times) so that the FETCH_SIZE / WRITE_SIZE counters can be
+        calibrated: factor = true KiB / counter KiB per dispatch.
+
+    python -m paper_1404_0027_amd.profiling summarize DB KERNEL_SUBSTR [--pmc]
+        Prints per-kernel dispatch count and mean/min/max duration from a
+        rocprofv3 kernel-trace database, or mean counter values per dispatch
+        (--pmc), for kernels whose name contains KERNEL_SUBSTR.
+
+    python -m paper_1404_0027_amd.profiling traffic FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB KERNEL OUT.json
+        Scales the kernel's FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by
+        the copy calibration and writes bytes per launch with a hash of the
+        kernel sources, so the benchmark only reports traffic measured on the
+        current kernels.
+"""
+from __future__ import annotations
+
+import glob
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_MIB = 64
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def copy_probe() -> None:
+    import torch
+
+    n = COPY_MIB * 1024 * 1024 // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty(n, device="cuda")
+    for _ in range(20):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copy probe: 20 x {COPY_MIB} MiB device-to-device copies done", flush=True)
+
+
+def _kernel_rows(db: str, substr: str):
+    c = sqlite3.connect(db)
+    return c.execute("select name, start, end from kernels where name like ?",
+                     (f"%{substr}%",)).fetchall()
+
+
+def _pmc_rows(db: str, substr: str):
+    c = sqlite3.connect(db)
+    return c.execute("select kernel_name, counter_name, avg(value), count(*) from counters_collection "
+                     "where kernel_name like ? group by kernel_name, counter_name",
+                     (f"%{substr}%",)).fetchall()
+
+
+def summarize(db: str, substr: str, pmc: bool = False) -> str:
+    lines = []
+    if pmc:
+        for name, counter, avg, n in _pmc_rows(db, substr):
+            lines.append(f"{name[:70]:70s} {counter:16s} mean {avg:14.1f} per dispatch (n={n})")
+        return "\n".join(lines)
+    rows = _kernel_rows(db, substr)
+    by = {}
+    for name, s, e in rows:
+        by.setdefault(name, []).append((e - s) / 1e3)
+    for name, d in sorted(by.items()):
+        d.sort()
+        lines.append(f"{name[:70]:70s} n={len(d):6d} mean {sum(d)/len(d):9.3f} us  "
+                     f"median {d[len(d)//2]:9.3f} us  min {d[0]:9.3f}  max {d[-1]:9.3f}")
+    return "\n".join(lines)
+
+
+def _counter(db: str, substr: str, counter: str) -> float:
+    vals = [avg for name, c, avg, n in _pmc_rows(db, substr) if c == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} for '{substr}' in {db}")
+    return vals[0]
+
+
+def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel, out_json) -> dict:
+    true_kib = COPY_MIB * 1024.0
+    f_factor = true_kib / _counter(copy_fetch_db, "copy", "FETCH_SIZE")
+    w_factor = true_kib / _counter(copy_write_db, "copy", "WRITE_SIZE")
+    fetch = _counter(fetch_db, kernel, "FETCH_SIZE") * f_factor * 1024.0
+    write = _counter(write_db, kernel, "WRITE_SIZE") * w_factor * 1024.0
+    rec = {"kernel": kernel, "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "bytes_per_launch": fetch + write, "fetch_calibration": f_factor,
+           "write_calibration": w_factor, "source_hash": source_hash()}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
+def main(argv: list[str]) -> int:
+    if not argv:
+        print(__doc__)
+        return 2
+    if argv[0] == "copy":
+        copy_probe()
+    elif argv[0] == "summarize":
+        print(summarize(argv[1], argv[2], pmc="--pmc" in argv))
+    elif argv[0] == "traffic":
+        print(json.dumps(traffic(*argv[1:7])))
+    elif argv[0] == "hash":
+        print(source_hash())
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
