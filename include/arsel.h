@@ -124,13 +124,15 @@ int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offse
 
 /*
  * Schedule of arsel_select_ragged (chosen by the autotuner).
- *   wave_max_m:  instances with M <= wave_max_m are run by one wavefront each;
- *                larger ones by a whole workgroup.
- *   block_waves: wavefronts per workgroup (1, 2, 4, 8 or 16).
- *   lds_max_m:   instances with M <= lds_max_m are staged in LDS; larger ones
- *                are gathered from global memory.
- *   blocks_per_cu: persistent workgroups launched per compute unit.
- * The schedule never changes results.
+ *   wave_max_m:  instances with M <= wave_max_m are run by one wavefront each
+ *                (staged in that wave's LDS slice); larger ones by a whole
+ *                workgroup.
+ *   block_waves: wavefronts per workgroup (4, 8 or 16).
+ *   lds_max_m:   workgroup instances with M <= lds_max_m are staged in LDS;
+ *                larger ones are gathered from global memory.
+ *   blocks_per_cu: persistent workgroups launched per compute unit (1..8).
+ * max(lds_max_m, block_waves * wave_max_m) floats of LDS must fit in one
+ * workgroup (ARSEL_ERR_ARG otherwise).  The schedule never changes results.
  */
 typedef struct {
     int32_t wave_max_m;

@@ -49,7 +49,7 @@ def lib() -> ctypes.CDLL:
         L.orc_philox4x32_10.restype = None
         L.orc_select_uniform.argtypes = [P, i64, i64, i64, i32, P, u64, u64, u32, u32, P, P, P, i32]
         L.orc_select_uniform.restype = i32
-        L.orc_select_ragged.argtypes = [P, P, i64, u64, u64, u32, P, P, P, i32]
+        L.orc_select_ragged.argtypes = [P, P, i64, P, u64, u64, u32, P, P, P, i32]
         L.orc_select_ragged.restype = i32
         L.orc_select_proposal.argtypes = [P, P, i64, i64, i64, i64, u64, u64, u32, P, P, i32]
         L.orc_select_proposal.restype = i32
@@ -106,15 +106,18 @@ def select_uniform(alpha: np.ndarray, M: int, K: int, ld: int, layout: int = AOS
 
 def select_ragged(alpha: np.ndarray, offsets: np.ndarray, *, seed: int, step: int = 0,
                   t_max: int = 4096, want_alpha0: bool = True, want_trials: bool = True,
-                  threads: int = 1):
+                  ids=None, threads: int = 1):
+    """Instance k = alpha[offsets[k]:offsets[k+1]]; with ids, only those instances
+    (outputs in the order of ids)."""
     a = np.ascontiguousarray(alpha, dtype=np.float32)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
-    K = off.shape[0] - 1
-    idx = np.empty(K, dtype=np.int32)
-    a0 = np.empty(K, dtype=np.float32) if want_alpha0 else None
-    tr = np.empty(K, dtype=np.uint32) if want_trials else None
-    rc = lib().orc_select_ragged(_p(a), _p(off), K, seed, step, t_max, _p(idx), _p(a0),
-                                 _p(tr), threads)
+    sel = None if ids is None else np.ascontiguousarray(ids, dtype=np.int64)
+    n = off.shape[0] - 1 if sel is None else sel.shape[0]
+    idx = np.empty(n, dtype=np.int32)
+    a0 = np.empty(n, dtype=np.float32) if want_alpha0 else None
+    tr = np.empty(n, dtype=np.uint32) if want_trials else None
+    rc = lib().orc_select_ragged(_p(a), _p(off), n, _p(sel), seed, step, t_max, _p(idx),
+                                 _p(a0), _p(tr), threads)
     if rc != 0:
         raise ValueError("orc_select_ragged rejected its arguments")
     return idx, a0, tr

@@ -275,28 +275,31 @@ int orc_select_uniform(const float *alpha, int64_t M, int64_t K, int64_t ld, int
     return 0;
 }
 
-/* Ragged batch: instance k is alpha[offsets[k] .. offsets[k+1]). */
-int orc_select_ragged(const float *alpha, const int64_t *offsets, int64_t K,
-                      uint64_t seed, uint64_t step, uint32_t t_max,
+/* Ragged batch: instance k is alpha[offsets[k] .. offsets[k+1]).  With ids,
+ * only instances ids[0..n) are selected (output i for instance ids[i]);
+ * otherwise all n instances in order. */
+int orc_select_ragged(const float *alpha, const int64_t *offsets, int64_t n,
+                      const int64_t *ids, uint64_t seed, uint64_t step, uint32_t t_max,
                       int32_t *index, float *alpha0, uint32_t *trials, int threads)
 {
-    if (K < 0) return -1;
+    if (n < 0) return -1;
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #pragma omp parallel for schedule(dynamic, 1) if (threads != 1)
 #endif
-    for (int64_t k = 0; k < K; ++k) {
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t k = ids ? ids[i] : i;
         int64_t M = offsets[k + 1] - offsets[k];
         if (M < 1) {
-            index[k] = -1;
-            if (alpha0) alpha0[k] = 0.0f;
-            if (trials) trials[k] = 0;
+            index[i] = M == 0 ? -1 : -2;
+            if (alpha0) alpha0[i] = M == 0 ? 0.0f : NAN;
+            if (trials) trials[i] = 0;
             continue;
         }
-        index[k] = select_uniform_one(alpha + offsets[k], 1, M, NULL, 0u, (uint32_t)k,
+        index[i] = select_uniform_one(alpha + offsets[k], 1, M, NULL, 0u, (uint32_t)k,
                                       seed, step, 0u, t_max,
-                                      alpha0 ? alpha0 + k : NULL,
-                                      trials ? trials + k : NULL);
+                                      alpha0 ? alpha0 + i : NULL,
+                                      trials ? trials + i : NULL);
     }
     return 0;
 }

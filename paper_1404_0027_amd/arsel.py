@@ -171,3 +171,52 @@ def get_schedule(device=None) -> Schedule:
 
 def set_schedule(s: Schedule, device=None) -> None:
     _check(lib().arsel_set_schedule(context(device), ctypes.byref(s)), "arsel_set_schedule")
+
+
+def select_ragged(alpha: torch.Tensor, offsets: torch.Tensor, *, seed: int, step: int = 0,
+                  t_max: int = 4096, host_offsets=None, want_alpha0: bool = False,
+                  want_trials: bool = False, index: torch.Tensor | None = None,
+                  alpha0: torch.Tensor | None = None, trials: torch.Tensor | None = None):
+    """Uneven batch in one persistent launch (arsel_select_ragged).
+
+    alpha: float32 CUDA tensor of concatenated instances; offsets: int64 CUDA
+    tensor [K+1].  host_offsets: the same offsets as a numpy array (optional);
+    when given, they are checked against alpha's size and the per-instance
+    sizes order the work longest first.
+    """
+    import numpy as np
+
+    dev = alpha.device
+    if not isinstance(offsets, torch.Tensor) or offsets.dtype != torch.int64:
+        raise ArselError("offsets must be an int64 tensor")
+    K = offsets.numel() - 1
+    if K < 0:
+        raise ArselError("offsets needs K+1 entries")
+    _need(offsets, torch.int64, K + 1, "offsets", dev)
+    _need(alpha, torch.float32, 0, "alpha", None)
+    sizes = None
+    if host_offsets is not None:
+        ho = np.ascontiguousarray(host_offsets, dtype=np.int64)
+        if ho.shape[0] != K + 1:
+            raise ArselError("host_offsets must have K+1 entries")
+        sizes = np.diff(ho)
+        if K > 0 and (ho[0] < 0 or np.any(sizes < 0) or ho[-1] > alpha.numel()):
+            raise ArselError("host_offsets must be non-decreasing and within alpha")
+        sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+    if index is None:
+        index = torch.empty(K, dtype=torch.int32, device=dev)
+    _need(index, torch.int32, K, "index", dev)
+    if want_alpha0 and alpha0 is None:
+        alpha0 = torch.empty(K, dtype=torch.float32, device=dev)
+    if alpha0 is not None:
+        _need(alpha0, torch.float32, K, "alpha0", dev)
+    if want_trials and trials is None:
+        trials = torch.empty(K, dtype=torch.int32, device=dev)
+    if trials is not None:
+        _need(trials, torch.int32, K, "trials", dev)
+    sp = None if sizes is None else sizes.ctypes.data_as(ctypes.c_void_p)
+    rc = lib().arsel_select_ragged(context(dev), _ptr(alpha), _ptr(offsets), K, sp,
+                                   seed & (2**64 - 1), step & (2**64 - 1), t_max, _ptr(index),
+                                   _ptr(alpha0), _ptr(trials), _stream(dev))
+    _check(rc, "arsel_select_ragged")
+    return index, alpha0, trials

@@ -27,13 +27,16 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     c->tile_lds_bytes = std::min<size_t>(c->lds_per_block, 80 * 1024);
     c->dense_tile = 16;
     c->dense_waves = 16;
-    c->sched.wave_max_m = 2048;
+    c->sched.wave_max_m = 1024;
     c->sched.block_waves = 8;
-    c->sched.lds_max_m = 16384;
+    c->sched.lds_max_m = 8192;
     c->sched.blocks_per_cu = 2;
     c->queue = nullptr;
     c->order = nullptr;
-    c->order_cap = 0;
+    c->order_bytes = 0;
+    c->staging = nullptr;
+    c->staging_bytes = 0;
+    c->staging_event = nullptr;
     if (hipMalloc((void **)&c->queue, 256) != hipSuccess) {
         delete c;
         (void)hipSetDevice(prev);
@@ -52,6 +55,11 @@ extern "C" int arsel_destroy(arsel_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->queue) (void)hipFree(ctx->queue);
     if (ctx->order) (void)hipFree(ctx->order);
+    if (ctx->staging_event) {
+        (void)hipEventSynchronize(ctx->staging_event);
+        (void)hipEventDestroy(ctx->staging_event);
+    }
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
     (void)hipSetDevice(prev);
     delete ctx;
     return ARSEL_OK;
@@ -84,10 +92,11 @@ extern "C" int arsel_set_schedule(arsel_ctx *ctx, const arsel_schedule *s)
 {
     if (!ctx || !s) return ARSEL_ERR_NULL;
     const int bw = s->block_waves;
-    if (!(bw == 1 || bw == 2 || bw == 4 || bw == 8 || bw == 16)) return ARSEL_ERR_ARG;
-    if (s->wave_max_m < 0 || s->lds_max_m < 0 || s->blocks_per_cu < 1 || s->blocks_per_cu > 8)
+    if (!(bw == 4 || bw == 8 || bw == 16)) return ARSEL_ERR_ARG;
+    if (s->wave_max_m < 1 || s->lds_max_m < 0 || s->blocks_per_cu < 1 || s->blocks_per_cu > 8)
         return ARSEL_ERR_ARG;
-    if ((size_t)s->lds_max_m * sizeof(float) > ctx->lds_per_block) return ARSEL_ERR_ARG;
+    const size_t lds = (size_t)std::max<int64_t>(s->lds_max_m, (int64_t)bw * s->wave_max_m) * sizeof(float);
+    if (lds + 2048 > ctx->lds_per_block) return ARSEL_ERR_ARG;
     ctx->sched = *s;
     return ARSEL_OK;
 }

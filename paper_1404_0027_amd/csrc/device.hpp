@@ -183,6 +183,28 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int lane)
            ((uint64_t)readlane_u32((uint32_t)(x >> 32), lane) << 32);
 }
 
+// Wave-uniform copy of a value (held in a scalar register).  Loop and branch
+// conditions of code that uses cross-lane operations are taken from such
+// values, so that the compiler keeps the wave converged around them.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    return (uint64_t)uniform_u32((uint32_t)x) | ((uint64_t)uniform_u32((uint32_t)(x >> 32)) << 32);
+}
+
+// Fetch-and-add executed by the whole (converged) wave: lane 0 adds v, the
+// other lanes add 0; every lane gets lane 0's old value, as a uniform value.
+// Works on global and LDS addresses.
+__device__ __forceinline__ uint32_t wave_fetch_add(uint32_t *p, uint32_t v)
+{
+    const uint32_t old = atomicAdd(p, (threadIdx.x & (kWave - 1)) == 0 ? v : 0u);
+    return uniform_u32(old);
+}
+
 __device__ __forceinline__ int first_lane(uint64_t mask)
 {
     return mask ? (int)__builtin_ctzll(mask) : kWave;

@@ -16,9 +16,12 @@ struct arsel_ctx {
     int dense_tile;           // instances per dense tile (upper bound)
     int dense_waves;          // wavefronts per dense workgroup (4, 8, 16)
     arsel_schedule sched;     // ragged schedule
-    uint32_t *queue;          // device work counter of the persistent ragged kernel
-    int32_t *order;           // device instance order (longest first), grown on demand
-    int32_t order_cap;
+    uint32_t *queue;          // device counters of the persistent ragged kernel (4 x u32)
+    int32_t *order;           // device work lists of the ragged kernel, grown on demand
+    size_t order_bytes;
+    int32_t *staging;         // pinned host staging of the work lists
+    size_t staging_bytes;
+    hipEvent_t staging_event; // completion of the last staging copy
 };
 
 namespace arsel {

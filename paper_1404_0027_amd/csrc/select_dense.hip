@@ -350,11 +350,11 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
     // schedule.  At most NW / (open instances) rounds of one instance run at
     // once: no speculative rounds while many instances are open, all waves on
     // the last ones.
-    if (readlane_u64(ts.open, 0) != 0) {
+    if (uniform_u64(ts.open) != 0) {
         int t = nk > 0 ? wave % nk : 0;
         for (;;) {
-            const uint64_t open = readlane_u64(
-                __hip_atomic_load(&ts.open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP), 0);
+            const uint64_t open = uniform_u64(
+                __hip_atomic_load(&ts.open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
             if (open == 0) break;
             const int cnt = __popcll(open);
             const uint32_t limit = (uint32_t)max(1, NW / cnt);
@@ -363,8 +363,8 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
             for (int c = 0; c < cnt && !found; ++c) {
                 const uint64_t hi = rest & (~0ull << t);
                 const int cand = (int)__builtin_ctzll(hi ? hi : rest);
-                const uint32_t inf = readlane_u32(__hip_atomic_load(&ts.inflight[cand], __ATOMIC_RELAXED,
-                                                                    __HIP_MEMORY_SCOPE_WORKGROUP), 0);
+                const uint32_t inf = uniform_u32(__hip_atomic_load(&ts.inflight[cand], __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_WORKGROUP));
                 if (inf < limit) {
                     t = cand;
                     found = true;
@@ -377,14 +377,10 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
                 __builtin_amdgcn_s_sleep(2);
                 continue;
             }
-            uint32_t r = 0;
-            if (lane == 0) {
-                atomicAdd(&ts.inflight[t], 1u);
-                r = atomicAdd(&ts.next[t], 1u);
-            }
-            r = readlane_u32(r, 0);
-            const uint64_t bk = readlane_u64(
-                __hip_atomic_load(&ts.best[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP), 0);
+            wave_fetch_add(&ts.inflight[t], 1u);
+            const uint32_t r = wave_fetch_add(&ts.next[t], 1u);
+            const uint64_t bk = uniform_u64(
+                __hip_atomic_load(&ts.best[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
             if (r >= rounds || (bk >> 32) < (uint64_t)r * kRoundTrials) {
                 if (lane == 0) {
                     atomicAnd((unsigned long long *)&ts.open, ~(1ull << t));

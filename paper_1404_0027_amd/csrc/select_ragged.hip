@@ -1,0 +1,261 @@
+// Uneven batches in one persistent launch.
+//
+// Instance k has M_k = offsets[k+1] - offsets[k] reactions (AoS).  The
+// instances are split into two work lists: large ones (M > wave_max_m) are
+// run by a whole workgroup (staged in LDS when M <= lds_max_m, otherwise
+// gathered from global memory right after the streaming pass that computes
+// the maximum), small ones by a single wavefront.  Persistent workgroups
+// take items from the two lists through atomic counters, the large list
+// first; with host-side sizes both lists are ordered longest first.  The
+// schedule (wave_max_m, waves per workgroup, lds_max_m, workgroups per CU) is
+// chosen by the autotuner and never changes the results: every instance
+// gets the same trial stream and rule as arsel_select with instance id k.
+#include <algorithm>
+#include <vector>
+
+#include "launch.hpp"
+#include "select_block.hpp"
+
+namespace arsel {
+
+struct RaggedArgs {
+    const float *alpha;
+    const int64_t *offsets;
+    const int32_t *list_block;   // instance ids of the workgroup list
+    const int32_t *list_wave;    // instance ids of the wavefront list
+    const uint32_t *counts;      // device list lengths (device-built lists), or null
+    uint32_t n_block, n_wave;    // host list lengths (host-built lists)
+    uint32_t *queue;             // [0] workgroup list cursor, [1] wavefront list cursor
+    int32_t *index;
+    float *alpha0;
+    uint32_t *trials;
+    uint64_t seed, step;
+    uint32_t t_max;
+    int32_t lds_max_m;
+    int32_t wave_max_m;
+};
+
+__global__ void k_ragged_reset(uint32_t *queue)
+{
+    if (threadIdx.x < 4) queue[threadIdx.x] = 0;
+}
+
+// Device-side split of the instances into the two lists (order arbitrary).
+__global__ void k_ragged_classify(const int64_t *offsets, int32_t K, int32_t wave_max_m,
+                                  int32_t *list_block, int32_t *list_wave, uint32_t *counts)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const int64_t m = offsets[k + 1] - offsets[k];
+    if (m > wave_max_m)
+        list_block[atomicAdd(&counts[0], 1u)] = k;
+    else
+        list_wave[atomicAdd(&counts[1], 1u)] = k;
+}
+
+__device__ __forceinline__ void ragged_write(const RaggedArgs &a, int k, const Outcome &o)
+{
+    a.index[k] = o.index;
+    if (a.alpha0) a.alpha0[k] = o.alpha0;
+    if (a.trials) a.trials[k] = o.trials;
+}
+
+// Sizes that cannot be processed (negative, or beyond 32-bit indexing).
+__device__ __forceinline__ bool bad_size(int64_t m)
+{
+    return m < 0 || m > 0x7FFFFFFF;
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_select_ragged(RaggedArgs a)
+{
+    extern __shared__ float lds[];
+    __shared__ BlockScratch<NW> bs;
+    __shared__ uint32_t item;
+    constexpr int NT = NW * 64;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = lane_id();
+    const uint32_t n_block = uniform_u32(a.counts ? a.counts[0] : a.n_block);
+    const uint32_t n_wave = uniform_u32(a.counts ? a.counts[1] : a.n_wave);
+    const bool want_a0 = a.alpha0 != nullptr;
+
+    // Large instances: the whole workgroup per instance.
+    for (;;) {
+        if (tid == 0) item = atomicAdd(&a.queue[0], 1u);
+        __syncthreads();
+        const uint32_t i = uniform_u32(item);
+        __syncthreads();
+        if (i >= n_block) break;
+        const int k = a.list_block[i];
+        const int64_t off = a.offsets[k];
+        const int64_t m64 = a.offsets[k + 1] - off;
+        if (bad_size(m64) || m64 == 0) {
+            if (tid == 0) {
+                Outcome o;
+                o.index = m64 == 0 ? -1 : -2;
+                o.alpha0 = m64 == 0 ? 0.0f : __builtin_nanf("");
+                o.trials = 0;
+                ragged_write(a, k, o);
+            }
+            continue;
+        }
+        const uint32_t M = (uint32_t)m64;
+        const float *row = a.alpha + off;
+        const bool staged = (int64_t)M <= (int64_t)a.lds_max_m;
+        // one streaming pass: bit-maximum (validity + alpha_max), staging into LDS
+        uint32_t mb = 0;
+        for (uint32_t j = tid; j < M; j += NT) {
+            const float x = __builtin_nontemporal_load(row + j);
+            mb = max(mb, __float_as_uint(x));
+            if (staged) lds[j] = x;
+        }
+        mb = block_max_u32<NW>(mb, bs);   // its barriers also publish the staged row
+        const Stream st = make_stream(a.seed, a.step, (uint32_t)k, kTagUniform);
+        const uint32_t hint = mb < 0x7F800000u ? mb : 0xFFFFFFFFu;
+        Outcome o;
+        if (staged)
+            o = block_select<NW>(ContigAcc{lds}, M, hint, st, a.t_max, want_a0, bs);
+        else
+            o = block_select<NW>(ContigAcc{row}, M, hint, st, a.t_max, want_a0, bs);
+        if (tid == 0) ragged_write(a, k, o);
+        __syncthreads();
+    }
+
+    // Small instances: one wavefront per instance, staged in the wave's LDS slice.
+    float *slice = lds + (size_t)wave * a.wave_max_m;
+    for (;;) {
+        const uint32_t i = wave_fetch_add(&a.queue[1], 1u);
+        if (i >= n_wave) break;
+        const int k = a.list_wave[i];
+        const int64_t off = a.offsets[k];
+        const int64_t m64 = a.offsets[k + 1] - off;
+        Outcome o;
+        if (bad_size(m64) || m64 == 0 || m64 > a.wave_max_m) {
+            o.index = m64 == 0 ? -1 : -2;
+            o.alpha0 = m64 == 0 ? 0.0f : __builtin_nanf("");
+            o.trials = 0;
+        } else {
+            const uint32_t M = (uint32_t)m64;
+            const float *row = a.alpha + off;
+            for (uint32_t j = lane; j < M; j += kWave) slice[j] = __builtin_nontemporal_load(row + j);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const Stream st = make_stream(a.seed, a.step, (uint32_t)k, kTagUniform);
+            o = wave_select(ContigAcc{slice}, M, nullptr, 0u, st, a.t_max, want_a0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (lane == 0) ragged_write(a, k, o);
+    }
+}
+
+template <int NW>
+static int launch_ragged(arsel_ctx *ctx, const RaggedArgs &a, size_t lds, hipStream_t s)
+{
+    const int grid = ctx->num_cu * ctx->sched.blocks_per_cu;
+    hipLaunchKernelGGL(k_select_ragged<NW>, dim3(grid), dim3(NW * 64), lds, s, a);
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
+
+// Grow a device buffer (contents not kept).
+static int grow(void **p, size_t *cap, size_t need)
+{
+    if (*cap >= need) return ARSEL_OK;
+    if (*p && hipFree(*p) != hipSuccess) return ARSEL_ERR_HIP;
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc(p, need) != hipSuccess) return ARSEL_ERR_ALLOC;
+    *cap = need;
+    return ARSEL_OK;
+}
+
+}  // namespace arsel
+
+using namespace arsel;
+
+extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offsets,
+                                   int32_t K, const int64_t *host_sizes, uint64_t seed,
+                                   uint64_t step, uint32_t t_max, int32_t *index, float *alpha0,
+                                   uint32_t *trials, void *stream)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    if (K < 0) return ARSEL_ERR_SIZE;
+    if (K == 0) return ARSEL_OK;
+    if (!alpha || !offsets || !index) return ARSEL_ERR_NULL;
+    int rc = ctx_activate(ctx);
+    if (rc) return rc;
+    const arsel_schedule &sc = ctx->sched;
+    const int nw = sc.block_waves;
+    const size_t lds = std::max<size_t>((size_t)sc.lds_max_m, (size_t)nw * sc.wave_max_m) * sizeof(float);
+    if (lds > ctx->lds_per_block - 2048) return ARSEL_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+
+    rc = grow((void **)&ctx->order, &ctx->order_bytes, 2 * (size_t)K * sizeof(int32_t));
+    if (rc) return rc;
+
+    RaggedArgs a;
+    a.alpha = alpha;
+    a.offsets = offsets;
+    a.list_block = ctx->order;
+    a.list_wave = ctx->order + K;
+    a.queue = ctx->queue;
+    a.index = index;
+    a.alpha0 = alpha0;
+    a.trials = trials;
+    a.seed = seed;
+    a.step = step;
+    a.t_max = t_max;
+    a.lds_max_m = sc.lds_max_m;
+    a.wave_max_m = sc.wave_max_m;
+
+    hipLaunchKernelGGL(k_ragged_reset, dim3(1), dim3(64), 0, s, ctx->queue);
+    if (host_sizes) {
+        // Longest first within each list; the lists go to the device through a
+        // pinned staging buffer (reused once the previous copy has finished).
+        std::vector<int32_t> blk, wav;
+        blk.reserve(K);
+        wav.reserve(K);
+        for (int32_t k = 0; k < K; ++k) (host_sizes[k] > sc.wave_max_m ? blk : wav).push_back(k);
+        auto longer = [&](int32_t x, int32_t y) {
+            return host_sizes[x] != host_sizes[y] ? host_sizes[x] > host_sizes[y] : x < y;
+        };
+        std::sort(blk.begin(), blk.end(), longer);
+        std::sort(wav.begin(), wav.end(), longer);
+        const size_t bytes = 2 * (size_t)K * sizeof(int32_t);
+        if (ctx->staging_event && hipEventSynchronize(ctx->staging_event) != hipSuccess)
+            return ARSEL_ERR_HIP;
+        if (ctx->staging_bytes < bytes) {
+            if (ctx->staging && hipHostFree(ctx->staging) != hipSuccess) return ARSEL_ERR_HIP;
+            ctx->staging = nullptr;
+            ctx->staging_bytes = 0;
+            if (hipHostMalloc((void **)&ctx->staging, bytes, hipHostMallocDefault) != hipSuccess)
+                return ARSEL_ERR_ALLOC;
+            ctx->staging_bytes = bytes;
+        }
+        std::copy(blk.begin(), blk.end(), ctx->staging);
+        std::copy(wav.begin(), wav.end(), ctx->staging + K);
+        if (hipMemcpyAsync(ctx->order, ctx->staging, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            return ARSEL_ERR_HIP;
+        if (!ctx->staging_event && hipEventCreateWithFlags(&ctx->staging_event, hipEventDisableTiming) != hipSuccess)
+            return ARSEL_ERR_HIP;
+        if (hipEventRecord(ctx->staging_event, s) != hipSuccess) return ARSEL_ERR_HIP;
+        a.counts = nullptr;
+        a.n_block = (uint32_t)blk.size();
+        a.n_wave = (uint32_t)wav.size();
+    } else {
+        hipLaunchKernelGGL(k_ragged_classify, dim3((K + 255) / 256), dim3(256), 0, s, offsets, K,
+                           sc.wave_max_m, ctx->order, ctx->order + K, ctx->queue + 2);
+        a.counts = ctx->queue + 2;
+        a.n_block = a.n_wave = 0;
+    }
+    if (hipGetLastError() != hipSuccess) return ARSEL_ERR_HIP;
+    switch (nw) {
+    case 4: return launch_ragged<4>(ctx, a, lds, s);
+    case 8: return launch_ragged<8>(ctx, a, lds, s);
+    case 16: return launch_ragged<16>(ctx, a, lds, s);
+    default: return ARSEL_ERR_ARG;
+    }
+}

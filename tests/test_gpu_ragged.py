@@ -1,0 +1,144 @@
+"""GPU parity of arsel_select_ragged (uneven batches, persistent launch)
+against the CPU oracle, bit for bit, under several schedules."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1404_0027_amd import arsel, workloads
+from tests.parity import assert_same
+
+pytestmark = pytest.mark.gpu
+
+
+def _ragged_both(alpha, offsets, *, seed, step, t_max=4096, host=True, ids=None):
+    a = torch.from_numpy(np.ascontiguousarray(alpha, np.float32)).cuda()
+    off = torch.from_numpy(np.ascontiguousarray(offsets, np.int64)).cuda()
+    idx, a0, tr = arsel.select_ragged(a, off, seed=seed, step=step, t_max=t_max,
+                                      host_offsets=offsets if host else None,
+                                      want_alpha0=True, want_trials=True)
+    torch.cuda.synchronize()
+    g = (idx.cpu().numpy(), a0.cpu().numpy(), tr.cpu().numpy().view(np.uint32))
+    if ids is not None:
+        g = tuple(x[ids] for x in g)
+    o = oracle.select_ragged(alpha, offsets, seed=seed, step=step, t_max=t_max, ids=ids,
+                             threads=8)
+    return g, o
+
+
+def _schedules():
+    return [(1024, 8, 8192, 2), (256, 4, 4096, 4), (4096, 8, 16384, 1), (64, 8, 0, 2),
+            (2048, 4, 2048, 1)]
+
+
+@pytest.fixture
+def restore_schedule(gpu):
+    s0 = arsel.get_schedule()
+    yield
+    arsel.set_schedule(s0)
+
+
+def test_ragged_mix_small(gpu):
+    rb = workloads.ragged_mix(K=400, seed=3, log2_lo=0, log2_hi=14)
+    for host in (True, False):
+        g, o = _ragged_both(rb.alpha, rb.offsets, seed=1, step=3, host=host)
+        assert_same(g, o, f"ragged host={host}")
+
+
+@pytest.mark.parametrize("sched", _schedules())
+def test_ragged_schedules_do_not_change_results(gpu, restore_schedule, sched):
+    rb = workloads.ragged_mix(K=300, seed=31, log2_lo=0, log2_hi=15)
+    s = arsel.Schedule(*sched)
+    arsel.set_schedule(s)
+    g, o = _ragged_both(rb.alpha, rb.offsets, seed=9, step=11)
+    assert_same(g, o, f"schedule {sched}")
+
+
+@pytest.mark.parametrize("t_max", [0, 1, 130, 1024])
+def test_ragged_fallbacks(gpu, t_max):
+    """Small budgets force the fixed-point fallback in both the wavefront and
+    the workgroup paths (staged and gathered from global memory)."""
+    rb = workloads.ragged_mix(K=120, seed=5, log2_lo=4, log2_hi=16)
+    g, o = _ragged_both(rb.alpha, rb.offsets, seed=2, step=t_max, t_max=t_max)
+    assert_same(g, o, f"t_max {t_max}")
+    if t_max == 0:
+        assert np.all((g[2] == 1) | (g[0] < 0))            # every selection fell back
+    if t_max == 1:
+        assert np.all((g[2] <= 2) | (g[0] < 0)) and np.any(g[2] == 2)
+
+
+def test_ragged_edge_instances(gpu):
+    rng = np.random.default_rng(7)
+    rows = [np.zeros(0), np.zeros(5), np.array([2.0]), rng.random(3000),
+            np.r_[rng.random(100), np.nan], np.r_[rng.random(20000), -1.0],
+            np.zeros(20000), np.full(70, 3e-44), rng.lognormal(0, 3, 40000),
+            np.r_[np.full(10, -0.0), 1.0], np.zeros(0), rng.random(64)]
+    sizes = np.array([len(r) for r in rows], np.int64)
+    offsets = np.zeros(len(rows) + 1, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    alpha = np.concatenate(rows).astype(np.float32)
+    for host in (True, False):
+        for t_max in (4096, 0):
+            g, o = _ragged_both(alpha, offsets, seed=4, step=1, t_max=t_max, host=host)
+            assert_same(g, o, f"edge host={host} t_max={t_max}")
+    assert g[0][0] == -1 and g[0][1] == -1 and g[0][2] == 0 and g[0][4] == -2 and g[0][5] == -2
+    assert g[0][6] == -1 and g[0][10] == -1 and g[0][9] == 10
+
+
+def test_ragged_full_size_sampled(gpu):
+    """10^4 instances, M log-uniform in [64, 65536] (about 9.4e7 propensities):
+    the whole batch in one launch, 400 sampled instances checked against the
+    oracle (instance ids preserved)."""
+    rb = workloads.ragged_mix(K=10000, seed=3)
+    rng = np.random.default_rng(0)
+    ids = np.sort(rng.choice(rb.K, size=400, replace=False))
+    ids = np.unique(np.r_[ids, np.argsort(rb.sizes())[-20:]])   # include the largest
+    g, o = _ragged_both(rb.alpha, rb.offsets, seed=1, step=0, ids=ids)
+    assert_same(g, o, "ragged full size (sampled)")
+
+
+def test_ragged_matches_dense(gpu):
+    """A ragged batch of equal sizes equals the dense AoS call (same instance ids)."""
+    rng = np.random.default_rng(12)
+    K, M = 64, 777
+    a = rng.exponential(1.0, size=(K, M)).astype(np.float32)
+    offsets = np.arange(K + 1, dtype=np.int64) * M
+    t = torch.from_numpy(a).cuda()
+    d = arsel.select(t, M, K, M, arsel.AOS, seed=3, step=5, want_alpha0=True, want_trials=True)
+    r = arsel.select_ragged(t.view(-1), torch.from_numpy(offsets).cuda(), seed=3, step=5,
+                            host_offsets=offsets, want_alpha0=True, want_trials=True)
+    for x, y in zip(d, r):
+        assert torch.equal(x, y)
+
+
+def test_ragged_argument_errors(gpu):
+    a = torch.ones(10, device="cuda")
+    with pytest.raises(arsel.ArselError):
+        arsel.select_ragged(a, torch.tensor([0, 5, 20], dtype=torch.int64, device="cuda"),
+                            seed=1, host_offsets=np.array([0, 5, 20]))   # beyond alpha
+    with pytest.raises(arsel.ArselError):
+        arsel.select_ragged(a, torch.tensor([0, 5, 3], dtype=torch.int64, device="cuda"),
+                            seed=1, host_offsets=np.array([0, 5, 3]))    # decreasing
+    bad = arsel.Schedule(1 << 20, 16, 0, 1)                               # LDS too large
+    with pytest.raises(arsel.ArselError):
+        arsel.set_schedule(bad)
+
+
+def test_autotuner_picks_a_valid_schedule_and_results_hold(gpu, restore_schedule, tmp_path,
+                                                            monkeypatch):
+    from paper_1404_0027_amd import autotune
+
+    monkeypatch.setattr(autotune, "CACHE_PATH", str(tmp_path / "cache.json"))
+    rb = workloads.ragged_mix(K=500, seed=8, log2_lo=4, log2_hi=16)
+    a = torch.from_numpy(rb.alpha).cuda()
+    off = torch.from_numpy(rb.offsets).cuda()
+    cands = [(256, 4, 0, 1), (1024, 8, 8192, 2), (2048, 8, 16384, 2)]
+    res = autotune.tune_ragged(a, off, rb.offsets, candidates=cands, reps=2)
+    assert res.schedule in cands and len(res.table) == len(cands)
+    assert tuple(arsel.get_schedule().__getattribute__(f) for f in
+                 ("wave_max_m", "block_waves", "lds_max_m", "blocks_per_cu")) == res.schedule
+    g, o = _ragged_both(rb.alpha, rb.offsets, seed=6, step=2)
+    assert_same(g, o, "tuned schedule")
+    # cached: the second call does not search
+    res2 = autotune.tune_ragged(a, off, rb.offsets, candidates=cands, reps=2)
+    assert res2.schedule == res.schedule and res2.table == []
