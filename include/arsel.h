@@ -144,6 +144,111 @@ typedef struct {
 int arsel_get_schedule(arsel_ctx *ctx, arsel_schedule *out);
 int arsel_set_schedule(arsel_ctx *ctx, const arsel_schedule *s);
 
+/*
+ * Acceptance-rejection with an integer proposal Q (the learned proposal):
+ * alpha[k*lda + j] (float) and Q[k*ldq + j] (uint32), DEVICE arrays.  Trial t
+ * (tag 1 stream) draws V uniform on [0, sum Q) by Lemire's rule on its
+ * candidate word, takes the least j with inclusive prefix P_j > V, and accepts
+ * when fl64(fl64(u c+) Q_j) < alpha_j, c+ = nextafter(max_j fl64(alpha_j/Q_j)),
+ * so the law is alpha_j / alpha_0 for any Q; after t_max rejected trials the
+ * same fixed-point inverse transform as arsel_select runs.  index: -4 when
+ * Q_j = 0 for some alpha_j > 0, or sum Q >= 2^32 (after the -2 / -1 checks).
+ * M up to ~13000 (alpha, Q and the prefix of one instance live in LDS);
+ * ARSEL_ERR_SIZE beyond.
+ */
+int arsel_select_proposal(arsel_ctx *ctx, const float *alpha, const uint32_t *Q, int32_t M,
+                          int32_t K, int64_t lda, int64_t ldq, uint64_t seed, uint64_t step,
+                          uint32_t t_max, int32_t *index, uint32_t *trials, void *stream);
+
+/* Mass-action network (DEVICE arrays of M entries): reaction j consumes
+ * species r0[j] and, when r1[j] >= 0, r1[j]; it produces p0[j] and, when
+ * p1[j] >= 0, p1[j].  Species indices must lie in [0, N). */
+typedef struct {
+    int32_t N, M;
+    const int32_t *r0, *r1, *p0, *p1;
+    const float *rate;
+} arsel_network;
+
+/* alpha[r*M + j] = rate_j * fl32(h_j(X[r])) with h = x_a, x_a x_b, or
+ * x_a (x_a - 1) / 2 (homodimer), computed in int64 and rounded to nearest. */
+int arsel_propensities(arsel_ctx *ctx, const arsel_network *net, const int32_t *X, int32_t R,
+                       float *alpha, void *stream);
+
+/* The SSA jump chain (the state sequence of the direct method, section "The
+ * Stochastic Simulation Algorithm") for R realizations in place on X
+ * (int32 [R][N]): step i of realization r selects by uniform AR on the tag-2
+ * stream (instance r, step step0 + i) and applies the stoichiometry; an
+ * outcome < 0 (nothing can fire) leaves the state.  rec_X (nullable) receives
+ * the state before each step i >= rec_from at [(i - rec_from)][r][:]; fired
+ * (nullable) the selection of each step at [i][r].  Bit-identical to the
+ * sequential definition. */
+int arsel_ssa_chain(arsel_ctx *ctx, const arsel_network *net, int32_t *X, int32_t R,
+                    uint64_t seed, uint64_t step0, int64_t steps, uint32_t t_max,
+                    int64_t rec_from, int32_t *rec_X, int32_t *fired, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned proposal (BF16 MLP on MFMA, FP32 accumulation).
+ *
+ * The acceptance-rejection rule stays exact with any proposal Q that covers
+ * the support: candidate j is drawn with probability Q_j / sum Q and accepted
+ * when u * c+ * Q_j < alpha_j with c+ >= max_j alpha_j / Q_j, so the selection
+ * law is alpha_j / alpha_0 whatever the network outputs; a good Q only raises
+ * the acceptance rate on skewed propensities.
+ * ------------------------------------------------------------------------ */
+
+/* Network description: DEVICE pointers.  f = bf16(log1p(X)) (N inputs,
+ * zero-padded to Kp), h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2),
+ * z = W3 h2 + b3 (M outputs, rows M..Mp-1 of W3 and b3 are padding).
+ * W1: bf16 [H][Kp], W2: bf16 [H][H], W3: bf16 [Mp][H] (row-major, bf16 stored
+ * as uint16); b1, b2: float [H]; b3: float [Mp]. */
+typedef struct {
+    int32_t N, M, H, Kp, Mp;
+    const void *W1, *W2, *W3;
+    const float *b1, *b2, *b3;
+} arsel_mlp;
+
+/* Forward pass for R states X (int32 [R][N] species counts, device) with
+ * their propensities alpha (float [R][M], device): q_out (nullable, float
+ * [R][M]) = softmax of z over the reactions with alpha_j > 0 (0 elsewhere);
+ * Q_out (nullable, uint32 [R][M]) = max(1, floor(q_j 2^(31-L))) on that
+ * support, 0 elsewhere, L = ceil(log2 M), so sum Q < 2^32.  Activations live
+ * in a context workspace (grown on demand). */
+int arsel_mlp_forward(arsel_ctx *ctx, const arsel_mlp *net, const int32_t *X, int32_t R,
+                      const float *alpha, float *q_out, uint32_t *Q_out, void *stream);
+
+/* Training state: the network (its W1, W2, W3 are the BF16 copies refreshed by
+ * each step) plus FP32 masters, gradients and Adam moments for the six
+ * parameters in the order W1, b1, W2, b2, W3, b3 (shapes as in arsel_mlp).
+ * All DEVICE pointers. */
+typedef struct {
+    arsel_mlp net;
+    float *master[6];
+    float *grad[6];
+    float *m[6];
+    float *v[6];
+    float beta1, beta2, eps;
+} arsel_mlp_train;
+
+/* One Adam step (t = 1, 2, ...) on a minibatch of B (state, propensity)
+ * pairs: loss = mean over rows of the cross-entropy -sum_j p_j log q_j with
+ * p = alpha / alpha_0 on the support; gradients by the backward GEMMs on
+ * MFMA; *loss (device float) receives the minibatch loss. */
+int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, const int32_t *X,
+                         const float *alpha, int32_t B, float lr, int32_t t, float *loss,
+                         void *stream);
+
+/* Refresh the BF16 copies (net.W1, W2, W3) from the FP32 masters
+ * (nearest-even rounding); used after initialising or loading masters. */
+int arsel_mlp_sync_bf16(arsel_ctx *ctx, const arsel_mlp_train *tr, void *stream);
+
+/* C = A . B^T-style product on MFMA: C[m][n] = sum_k A(m,k) B(n,k), BF16 A and
+ * B (device), FP32 C [M][ldc]; A(m,k) = A[m*lda+k] if a_kcontig else
+ * A[k*lda+m]; B(n,k) = B[n*ldb+k] if b_kcontig else B[k*ldb+n]; optional
+ * bias[n] and ReLU.  The building block of the MLP kernels. */
+int arsel_gemm_bf16(arsel_ctx *ctx, const void *A, int64_t lda, int32_t a_kcontig, const void *B,
+                    int64_t ldb, int32_t b_kcontig, int32_t M, int32_t N, int32_t K,
+                    const float *bias, int32_t relu, float *C, int64_t ldc, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,8 +61,41 @@ class Schedule(ctypes.Structure):
                 ("lds_max_m", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
+class Network(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("r0", ctypes.c_void_p),
+                ("r1", ctypes.c_void_p), ("p0", ctypes.c_void_p), ("p1", ctypes.c_void_p),
+                ("rate", ctypes.c_void_p)]
+
+
+class MLP(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("Kp", ctypes.c_int32), ("Mp", ctypes.c_int32), ("W1", ctypes.c_void_p),
+                ("W2", ctypes.c_void_p), ("W3", ctypes.c_void_p), ("b1", ctypes.c_void_p),
+                ("b2", ctypes.c_void_p), ("b3", ctypes.c_void_p)]
+
+
+class MLPTrain(ctypes.Structure):
+    _fields_ = [("net", MLP), ("master", ctypes.c_void_p * 6), ("grad", ctypes.c_void_p * 6),
+                ("m", ctypes.c_void_p * 6), ("v", ctypes.c_void_p * 6),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 _P = ctypes.c_void_p
 _EXTRA_SIGNATURES = {
+    "arsel_select_proposal": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                              ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                              _P, _P, _P],
+    "arsel_propensities": [_P, ctypes.POINTER(Network), _P, ctypes.c_int32, _P, _P],
+    "arsel_ssa_chain": [_P, ctypes.POINTER(Network), _P, ctypes.c_int32, ctypes.c_uint64,
+                        ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int64, _P, _P,
+                        _P],
+    "arsel_mlp_forward": [_P, ctypes.POINTER(MLP), _P, ctypes.c_int32, _P, _P, _P, _P],
+    "arsel_mlp_train_step": [_P, ctypes.POINTER(MLPTrain), _P, _P, ctypes.c_int32, ctypes.c_float,
+                             ctypes.c_int32, _P, _P],
+    "arsel_mlp_sync_bf16": [_P, ctypes.POINTER(MLPTrain), _P],
+    "arsel_gemm_bf16": [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32,
+                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32, _P,
+                        ctypes.c_int64, _P],
     "arsel_select_ragged": [_P, _P, _P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64,
                             ctypes.c_uint32, _P, _P, _P, _P],
     "arsel_get_schedule": [_P, ctypes.POINTER(Schedule)],
@@ -220,3 +253,53 @@ def select_ragged(alpha: torch.Tensor, offsets: torch.Tensor, *, seed: int, step
                                    _ptr(alpha0), _ptr(trials), _stream(dev))
     _check(rc, "arsel_select_ragged")
     return index, alpha0, trials
+
+
+def select_proposal(alpha: torch.Tensor, Q: torch.Tensor, *, seed: int, step: int = 0,
+                    t_max: int = 4096, want_trials: bool = False,
+                    index: torch.Tensor | None = None, trials: torch.Tensor | None = None):
+    """AR with the integer proposal Q (arsel_select_proposal).  alpha float32
+    [K, M] and Q int32/uint32 bit patterns [K, M], both CUDA and contiguous."""
+    if alpha.dim() != 2 or Q.shape != alpha.shape:
+        raise ArselError("alpha and Q must be [K, M] tensors of the same shape")
+    K, M = alpha.shape
+    dev = alpha.device
+    _need(alpha, torch.float32, K * M, "alpha", dev)
+    if Q.dtype not in (torch.int32, torch.uint32):
+        raise ArselError("Q must hold 32-bit integers")
+    if not Q.is_contiguous() or Q.device != dev:
+        raise ArselError("Q must be contiguous on the same GPU")
+    if index is None:
+        index = torch.empty(K, dtype=torch.int32, device=dev)
+    _need(index, torch.int32, K, "index", dev)
+    if want_trials and trials is None:
+        trials = torch.empty(K, dtype=torch.int32, device=dev)
+    if trials is not None:
+        _need(trials, torch.int32, K, "trials", dev)
+    rc = lib().arsel_select_proposal(context(dev), _ptr(alpha), _ptr(Q), M, K, M, M,
+                                     seed & (2**64 - 1), step & (2**64 - 1), t_max, _ptr(index),
+                                     _ptr(trials), _stream(dev))
+    _check(rc, "arsel_select_proposal")
+    return index, trials
+
+
+def gemm_bf16(A: torch.Tensor, lda: int, a_kcontig: bool, B: torch.Tensor, ldb: int,
+              b_kcontig: bool, M: int, N: int, K: int, bias=None, relu=False, C=None):
+    """C[m][n] = sum_k A(m,k) B(n,k) on MFMA (see arsel_gemm_bf16)."""
+    dev = A.device
+    if A.dtype != torch.bfloat16 or B.dtype != torch.bfloat16:
+        raise ArselError("A and B must be bfloat16")
+    need_a = (M - 1) * lda + K if a_kcontig else (K - 1) * lda + M
+    need_b = (N - 1) * ldb + K if b_kcontig else (K - 1) * ldb + N
+    if A.numel() < need_a or B.numel() < need_b:
+        raise ArselError("operand too small for the given shape")
+    if C is None:
+        C = torch.empty(M, N, dtype=torch.float32, device=dev)
+    _need(C, torch.float32, M * N, "C", dev)
+    if bias is not None:
+        _need(bias, torch.float32, N, "bias", dev)
+    rc = lib().arsel_gemm_bf16(context(dev), _ptr(A), lda, int(a_kcontig), _ptr(B), ldb,
+                               int(b_kcontig), M, N, K, _ptr(bias), int(relu), _ptr(C), N,
+                               _stream(dev))
+    _check(rc, "arsel_gemm_bf16")
+    return C

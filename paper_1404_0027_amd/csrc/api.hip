@@ -37,6 +37,8 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     c->staging = nullptr;
     c->staging_bytes = 0;
     c->staging_event = nullptr;
+    c->ws = nullptr;
+    c->ws_bytes = 0;
     if (hipMalloc((void **)&c->queue, 256) != hipSuccess) {
         delete c;
         (void)hipSetDevice(prev);
@@ -60,6 +62,7 @@ extern "C" int arsel_destroy(arsel_ctx *ctx)
         (void)hipEventDestroy(ctx->staging_event);
     }
     if (ctx->staging) (void)hipHostFree(ctx->staging);
+    if (ctx->ws) (void)hipFree(ctx->ws);
     (void)hipSetDevice(prev);
     delete ctx;
     return ARSEL_OK;

@@ -22,6 +22,8 @@ struct arsel_ctx {
     int32_t *staging;         // pinned host staging of the work lists
     size_t staging_bytes;
     hipEvent_t staging_event; // completion of the last staging copy
+    void *ws;                 // MLP workspace (activations, gradients), grown on demand
+    size_t ws_bytes;
 };
 
 namespace arsel {

@@ -1,0 +1,489 @@
+// Learned proposal: a small BF16 MLP on MFMA (FP32 accumulation) that maps
+// species counts to a proposal q over reactions, its integer quantisation Q,
+// and its training (forward, cross-entropy gradient, backward GEMMs, Adam).
+//
+// Acceptance-rejection stays exact with ANY proposal that covers the support:
+// a candidate j drawn with probability Q_j / sum Q is accepted with
+// probability alpha_j / (c+ Q_j), c+ >= max alpha_j / Q_j, so the network only
+// changes the acceptance rate, never the selection law.
+//
+// Network: f = bf16(log1p(X)) (N inputs, zero-padded to Kp), h1 = relu(W1 f + b1),
+// h2 = relu(W2 h1 + b2), z = W3 h2 + b3 (M outputs, padded to Mp); q = softmax(z)
+// over the reactions with alpha_j > 0; Q_j = max(1, floor(q_j 2^(31-L))) on
+// that support (L = ceil(log2 M)), 0 elsewhere, so sum Q < 2^32.
+#include <math.h>
+
+#include "launch.hpp"
+#include "device.hpp"
+
+namespace arsel {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4m __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// GEMM: C[m][n] = sum_k A(m, k) B(n, k), BF16 inputs, FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16.  A(m,k) = A[m*lda + k] when A_KC (k contiguous)
+// else A[k*lda + m]; B(n,k) = B[n*ldb + k] when B_KC else B[k*ldb + n].
+// Workgroup tile 64 x 64, 4 wavefronts of 32 x 32 (2 x 2 MFMA blocks), K step 32.
+// Epilogue: + bias[n], ReLU, zero where mask(m, n) <= 0, FP32 and/or BF16 out.
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+    const __bf16 *A;
+    const __bf16 *B;
+    int64_t lda, ldb;
+    int32_t M, N, K;
+    const float *bias;        // [N] or null
+    const __bf16 *mask;       // [M][ldm] or null
+    int64_t ldm;
+    float *C;                 // [M][ldc] or null
+    int64_t ldc;
+    __bf16 *Cb;               // [M][ldcb] or null
+    int64_t ldcb;
+    int32_t relu;
+};
+
+constexpr int kGT = 64;      // tile edge
+constexpr int kGK = 32;      // k step
+constexpr int kGPad = 8;     // LDS row padding (bf16)
+
+template <bool KC>
+__device__ __forceinline__ void gemm_load_tile(const __bf16 *X, int64_t ld, int rows, int K, int r0,
+                                               int k0, __bf16 (*S)[kGK + kGPad])
+{
+    const int t = threadIdx.x;   // 256 threads, 64 x 32 elements, 8 per thread
+    if (KC) {
+        const int r = t >> 2, kk = (t & 3) * 8;
+        const int gr = r0 + r, gk = k0 + kk;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            S[r][kk + e] = (gr < rows && gk + e < K) ? X[(int64_t)gr * ld + gk + e] : (__bf16)0.0f;
+    } else {
+        const int kk = t >> 3, rr = (t & 7) * 8;
+        const int gk = k0 + kk;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int gr = r0 + rr + e;
+            S[rr + e][kk] = (gr < rows && gk < K) ? X[(int64_t)gk * ld + gr] : (__bf16)0.0f;
+        }
+    }
+}
+
+template <bool A_KC, bool B_KC>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
+{
+    __shared__ __bf16 sA[kGT][kGK + kGPad];
+    __shared__ __bf16 sB[kGT][kGK + kGPad];
+    const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4m acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4m){0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < g.K; k0 += kGK) {
+        gemm_load_tile<A_KC>(g.A, g.lda, g.M, g.K, m0, k0, sA);
+        gemm_load_tile<B_KC>(g.B, g.ldb, g.N, g.K, n0, k0, sB);
+        __syncthreads();
+        const int kq = (lane >> 4) * 8, rl = lane & 15;
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[i][e] = sA[wm + 16 * i + rl][kq + e];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) b[j][e] = sB[wn + 16 * j + rl][kq + e];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // D layout: lane holds rows 4*(lane/16) + r, column lane % 16 of each 16 x 16 block.
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int n = n0 + wn + 16 * j + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][j][r];
+                if (g.bias) v += g.bias[n];
+                if (g.relu) v = v > 0.f ? v : 0.f;
+                if (g.mask && !((float)g.mask[(int64_t)m * g.ldm + n] > 0.f)) v = 0.f;
+                if (g.C) g.C[(int64_t)m * g.ldc + n] = v;
+                if (g.Cb) g.Cb[(int64_t)m * g.ldcb + n] = (__bf16)v;
+            }
+}
+
+static int gemm(const GemmArgs &g, bool a_kc, bool b_kc, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0) return ARSEL_OK;
+    dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT);
+    if (a_kc && b_kc) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, s, g);
+    else if (a_kc) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, g);
+    else if (b_kc) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, g);
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
+
+static GemmArgs gemm_args(const void *A, int64_t lda, const void *B, int64_t ldb, int M, int N, int K)
+{
+    GemmArgs g{};
+    g.A = (const __bf16 *)A;
+    g.B = (const __bf16 *)B;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise and row kernels.
+// ---------------------------------------------------------------------------
+
+// F[r][i] = bf16(log1p(X[r][i])) for i < N, 0 for N <= i < Kp.
+__global__ void k_features(const int32_t *X, int32_t R, int32_t N, int32_t Kp, __bf16 *F)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)R * Kp) return;
+    const int64_t r = idx / Kp;
+    const int i = (int)(idx - r * Kp);
+    float v = 0.0f;
+    if (i < N) {
+        const int32_t x = X[r * N + i];
+        v = log1pf((float)(x > 0 ? x : 0));
+    }
+    F[idx] = (__bf16)v;
+}
+
+// One wavefront per row: masked softmax of z over alpha_j > 0, then Q.
+// For training (p_grad != null): dz_j = (q_j - p_j) * scale with
+// p_j = alpha_j / sum alpha (FP32), written as BF16 and FP32; the row's
+// cross-entropy -sum p_j log q_j is added to *loss (scaled).
+__global__ void k_softmax_quant(const float *Z, int64_t ldz, const float *alpha, int32_t R,
+                                int32_t M, int32_t L, float *q_out, uint32_t *Q_out,
+                                __bf16 *dz_b, float *dz_f, int64_t lddz, float scale,
+                                float *loss)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (r >= R) return;
+    const float *z = Z + r * ldz;
+    const float *a = alpha + r * M;
+    float zmax = -INFINITY, asum = 0.0f;
+    for (int j = lane; j < M; j += 64) {
+        if (a[j] > 0.0f) {
+            zmax = fmaxf(zmax, z[j]);
+            asum += a[j];
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        zmax = fmaxf(zmax, __shfl_xor(zmax, off, 64));
+        asum += __shfl_xor(asum, off, 64);
+    }
+    float esum = 0.0f;
+    for (int j = lane; j < M; j += 64)
+        if (a[j] > 0.0f) esum += expf(z[j] - zmax);
+    for (int off = 32; off >= 1; off >>= 1) esum += __shfl_xor(esum, off, 64);
+    const float qscale = ldexpf(1.0f, 31 - L);
+    const float lse = zmax + logf(esum);
+    float ce = 0.0f;
+    for (int j = lane; j < M; j += 64) {
+        const bool sup = a[j] > 0.0f;
+        const float q = sup ? expf(z[j] - zmax) / esum : 0.0f;
+        if (q_out) q_out[r * M + j] = q;
+        if (Q_out) {
+            uint32_t Q = 0;
+            if (sup) {
+                const float f = floorf(q * qscale);
+                Q = f < 1.0f ? 1u : (uint32_t)f;
+            }
+            Q_out[r * M + j] = Q;
+        }
+        if (dz_b || dz_f) {
+            const float p = sup ? a[j] / asum : 0.0f;
+            const float d = (q - p) * scale;
+            if (dz_b) dz_b[r * lddz + j] = (__bf16)d;
+            if (dz_f) dz_f[r * lddz + j] = d;
+            if (sup && p > 0.0f) ce -= p * (z[j] - lse);
+        }
+    }
+    // padded logits (M <= j < lddz) carry no gradient
+    for (int j = M + lane; j < lddz; j += 64) {
+        if (dz_b) dz_b[r * lddz + j] = (__bf16)0.0f;
+        if (dz_f) dz_f[r * lddz + j] = 0.0f;
+    }
+    if (loss) {
+        for (int off = 32; off >= 1; off >>= 1) ce += __shfl_xor(ce, off, 64);
+        if (lane == 0) atomicAdd(loss, ce * scale);
+    }
+}
+
+// Column sums of a [R][ld] FP32 matrix (bias gradients): out[n] = sum_r D[r][n].
+__global__ void k_colsum(const float *D, int64_t ld, int32_t R, int32_t N, float *out)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int r = 0; r < R; ++r) s += D[(int64_t)r * ld + n];
+    out[n] = s;
+}
+
+// Adam on FP32 master weights (bias-corrected), refreshing the BF16 copy.
+__global__ void k_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, int64_t n,
+                       float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = (__bf16)wi;
+}
+
+__global__ void k_zero_f32(float *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+static inline dim3 grid1(int64_t n, int b = 256)
+{
+    return dim3((unsigned)((n + b - 1) / b));
+}
+
+// Workspace carved from one context-owned buffer.
+struct Carver {
+    char *base;
+    size_t off;
+    template <class T>
+    T *take(size_t n)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = (T *)(base + off);
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+static int ensure_ws(arsel_ctx *ctx, size_t bytes)
+{
+    if (ctx->ws_bytes >= bytes) return ARSEL_OK;
+    if (ctx->ws && hipFree(ctx->ws) != hipSuccess) return ARSEL_ERR_HIP;
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    if (hipMalloc(&ctx->ws, bytes) != hipSuccess) return ARSEL_ERR_ALLOC;
+    ctx->ws_bytes = bytes;
+    return ARSEL_OK;
+}
+
+static int check_mlp(const arsel_mlp *n)
+{
+    if (!n || !n->W1 || !n->W2 || !n->W3 || !n->b1 || !n->b2 || !n->b3) return ARSEL_ERR_NULL;
+    if (n->N < 1 || n->M < 1 || n->H < 1 || n->Kp < n->N || n->Mp < n->M) return ARSEL_ERR_SIZE;
+    return ARSEL_OK;
+}
+
+static int ceil_log2_host(int32_t m)
+{
+    int L = 0;
+    while ((1ll << L) < m) ++L;
+    return L;
+}
+
+// Forward pass into the workspace; returns pointers to F, H1, H2, Z.
+struct Fwd {
+    __bf16 *F, *H1, *H2;
+    float *Z;
+};
+
+static int forward(arsel_ctx *ctx, const arsel_mlp *n, const int32_t *X, int32_t R, Carver &cv,
+                   Fwd &f, hipStream_t s)
+{
+    f.F = cv.take<__bf16>((size_t)R * n->Kp);
+    f.H1 = cv.take<__bf16>((size_t)R * n->H);
+    f.H2 = cv.take<__bf16>((size_t)R * n->H);
+    f.Z = cv.take<float>((size_t)R * n->Mp);
+    (void)ctx;
+    hipLaunchKernelGGL(k_features, grid1((int64_t)R * n->Kp), dim3(256), 0, s, X, R, n->N, n->Kp, f.F);
+    GemmArgs g = gemm_args(f.F, n->Kp, n->W1, n->Kp, R, n->H, n->Kp);
+    g.bias = n->b1;
+    g.relu = 1;
+    g.Cb = f.H1;
+    g.ldcb = n->H;
+    int rc = gemm(g, true, true, s);
+    if (rc) return rc;
+    g = gemm_args(f.H1, n->H, n->W2, n->H, R, n->H, n->H);
+    g.bias = n->b2;
+    g.relu = 1;
+    g.Cb = f.H2;
+    g.ldcb = n->H;
+    if ((rc = gemm(g, true, true, s))) return rc;
+    g = gemm_args(f.H2, n->H, n->W3, n->H, R, n->Mp, n->H);
+    g.bias = n->b3;
+    g.C = f.Z;
+    g.ldc = n->Mp;
+    return gemm(g, true, true, s);
+}
+
+static size_t fwd_bytes(const arsel_mlp *n, int32_t R)
+{
+    return (size_t)R * (n->Kp * 2 + n->H * 4 + n->Mp * 4) + 8 * 256;
+}
+
+}  // namespace arsel
+
+using namespace arsel;
+
+extern "C" int arsel_mlp_forward(arsel_ctx *ctx, const arsel_mlp *net, const int32_t *X, int32_t R,
+                                 const float *alpha, float *q_out, uint32_t *Q_out, void *stream)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    int rc = check_mlp(net);
+    if (rc) return rc;
+    if (R < 0) return ARSEL_ERR_SIZE;
+    if (R == 0) return ARSEL_OK;
+    if (!X || !alpha || (!q_out && !Q_out)) return ARSEL_ERR_NULL;
+    if ((rc = ctx_activate(ctx))) return rc;
+    if ((rc = ensure_ws(ctx, fwd_bytes(net, R)))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Carver cv{(char *)ctx->ws, 0};
+    Fwd f;
+    if ((rc = forward(ctx, net, X, R, cv, f, s))) return rc;
+    hipLaunchKernelGGL(k_softmax_quant, dim3((R + 3) / 4), dim3(256), 0, s, f.Z, (int64_t)net->Mp,
+                       alpha, R, net->M, ceil_log2_host(net->M), q_out, Q_out, (__bf16 *)nullptr,
+                       (float *)nullptr, (int64_t)0, 0.0f, (float *)nullptr);
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
+
+extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, const int32_t *X,
+                                    const float *alpha, int32_t B, float lr, int32_t t,
+                                    float *loss, void *stream)
+{
+    if (!ctx || !tr) return ARSEL_ERR_NULL;
+    const arsel_mlp *n = &tr->net;
+    int rc = check_mlp(n);
+    if (rc) return rc;
+    if (B < 1 || t < 1) return ARSEL_ERR_SIZE;
+    if (!X || !alpha || !loss) return ARSEL_ERR_NULL;
+    for (int i = 0; i < 6; ++i)
+        if (!tr->master[i] || !tr->grad[i] || !tr->m[i] || !tr->v[i]) return ARSEL_ERR_NULL;
+    if ((rc = ctx_activate(ctx))) return rc;
+    const size_t extra = (size_t)B * (n->Mp * 6 + n->H * 12) + 8 * 256;
+    if ((rc = ensure_ws(ctx, fwd_bytes(n, B) + extra))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Carver cv{(char *)ctx->ws, 0};
+    Fwd f;
+    if ((rc = forward(ctx, n, X, B, cv, f, s))) return rc;
+    __bf16 *dZb = cv.take<__bf16>((size_t)B * n->Mp);
+    float *dZf = cv.take<float>((size_t)B * n->Mp);
+    __bf16 *dH2 = cv.take<__bf16>((size_t)B * n->H);
+    float *dH2f = cv.take<float>((size_t)B * n->H);
+    __bf16 *dH1 = cv.take<__bf16>((size_t)B * n->H);
+    float *dH1f = cv.take<float>((size_t)B * n->H);
+
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, loss, (int64_t)1);
+    const float scale = 1.0f / (float)B;
+    hipLaunchKernelGGL(k_softmax_quant, dim3((B + 3) / 4), dim3(256), 0, s, f.Z, (int64_t)n->Mp, alpha,
+                       B, n->M, ceil_log2_host(n->M), (float *)nullptr, (uint32_t *)nullptr, dZb, dZf,
+                       (int64_t)n->Mp, scale, loss);
+    // gradients: grad[0..5] = dW1, db1, dW2, db2, dW3, db3 (FP32, shapes of the masters)
+    GemmArgs g = gemm_args(dZb, n->Mp, f.H2, n->H, n->Mp, n->H, B);     // dW3 = dZ^T H2
+    g.C = tr->grad[4];
+    g.ldc = n->H;
+    if ((rc = gemm(g, false, false, s))) return rc;
+    hipLaunchKernelGGL(k_colsum, grid1(n->Mp), dim3(256), 0, s, dZf, (int64_t)n->Mp, B, n->Mp, tr->grad[5]);
+    g = gemm_args(dZb, n->Mp, n->W3, n->H, B, n->H, n->Mp);              // dH2 = dZ W3 . [h2 > 0]
+    g.mask = f.H2;
+    g.ldm = n->H;
+    g.Cb = dH2;
+    g.ldcb = n->H;
+    g.C = dH2f;
+    g.ldc = n->H;
+    if ((rc = gemm(g, true, false, s))) return rc;
+    g = gemm_args(dH2, n->H, f.H1, n->H, n->H, n->H, B);                 // dW2 = dH2^T H1
+    g.C = tr->grad[2];
+    g.ldc = n->H;
+    if ((rc = gemm(g, false, false, s))) return rc;
+    hipLaunchKernelGGL(k_colsum, grid1(n->H), dim3(256), 0, s, dH2f, (int64_t)n->H, B, n->H, tr->grad[3]);
+    g = gemm_args(dH2, n->H, n->W2, n->H, B, n->H, n->H);                // dH1 = dH2 W2 . [h1 > 0]
+    g.mask = f.H1;
+    g.ldm = n->H;
+    g.Cb = dH1;
+    g.ldcb = n->H;
+    g.C = dH1f;
+    g.ldc = n->H;
+    if ((rc = gemm(g, true, false, s))) return rc;
+    g = gemm_args(dH1, n->H, f.F, n->Kp, n->H, n->Kp, B);                // dW1 = dH1^T F
+    g.C = tr->grad[0];
+    g.ldc = n->Kp;
+    if ((rc = gemm(g, false, false, s))) return rc;
+    hipLaunchKernelGGL(k_colsum, grid1(n->H), dim3(256), 0, s, dH1f, (int64_t)n->H, B, n->H, tr->grad[1]);
+
+    const int64_t sizes[6] = {(int64_t)n->H * n->Kp, n->H, (int64_t)n->H * n->H, n->H,
+                              (int64_t)n->Mp * n->H, n->Mp};
+    __bf16 *copies[6] = {(__bf16 *)n->W1, nullptr, (__bf16 *)n->W2, nullptr, (__bf16 *)n->W3, nullptr};
+    const float c1 = 1.0f - powf(tr->beta1, (float)t), c2 = 1.0f - powf(tr->beta2, (float)t);
+    for (int i = 0; i < 6; ++i)
+        hipLaunchKernelGGL(k_adam, grid1(sizes[i]), dim3(256), 0, s, tr->master[i], tr->grad[i], tr->m[i],
+                           tr->v[i], copies[i], sizes[i], lr, tr->beta1, tr->beta2, tr->eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
+
+// Plain GEMM entry (tests and tools): C = A . B with the layout flags above.
+extern "C" int arsel_gemm_bf16(arsel_ctx *ctx, const void *A, int64_t lda, int32_t a_kcontig,
+                               const void *B, int64_t ldb, int32_t b_kcontig, int32_t M, int32_t N,
+                               int32_t K, const float *bias, int32_t relu, float *C, int64_t ldc,
+                               void *stream)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    if (M < 0 || N < 0 || K < 0) return ARSEL_ERR_SIZE;
+    if (!A || !B || !C) return ARSEL_ERR_NULL;
+    int rc = ctx_activate(ctx);
+    if (rc) return rc;
+    GemmArgs g = gemm_args(A, lda, B, ldb, M, N, K);
+    g.bias = bias;
+    g.relu = relu;
+    g.C = C;
+    g.ldc = ldc;
+    return gemm(g, a_kcontig != 0, b_kcontig != 0, (hipStream_t)stream);
+}
+
+namespace arsel {
+__global__ void k_cast_bf16(const float *w, __bf16 *wb, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wb[i] = (__bf16)w[i];
+}
+}  // namespace arsel
+
+// Refresh the BF16 copies W1, W2, W3 of a training state from its FP32 masters.
+extern "C" int arsel_mlp_sync_bf16(arsel_ctx *ctx, const arsel_mlp_train *tr, void *stream)
+{
+    if (!ctx || !tr) return ARSEL_ERR_NULL;
+    const arsel_mlp *n = &tr->net;
+    int rc = check_mlp(n);
+    if (rc) return rc;
+    if (!tr->master[0] || !tr->master[2] || !tr->master[4]) return ARSEL_ERR_NULL;
+    if ((rc = ctx_activate(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n1 = (int64_t)n->H * n->Kp, n2 = (int64_t)n->H * n->H, n3 = (int64_t)n->Mp * n->H;
+    hipLaunchKernelGGL(k_cast_bf16, grid1(n1), dim3(256), 0, s, tr->master[0], (__bf16 *)n->W1, n1);
+    hipLaunchKernelGGL(k_cast_bf16, grid1(n2), dim3(256), 0, s, tr->master[2], (__bf16 *)n->W2, n2);
+    hipLaunchKernelGGL(k_cast_bf16, grid1(n3), dim3(256), 0, s, tr->master[4], (__bf16 *)n->W3, n3);
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}

@@ -1,0 +1,189 @@
+// Acceptance-rejection with an integer proposal Q (the learned proposal).
+//
+// Trial t of instance k at step s uses the tag-1 stream: its candidate word w
+// gives V = hi32(w * sum Q) (rejected when lo32 < 2^32 mod sum Q, so V is
+// exactly uniform on [0, sum Q)), the candidate is the least j with inclusive
+// prefix P_j > V (probability Q_j / sum Q), and it is accepted when
+// fl64(fl64(u c+) Q_j) < alpha_j with c+ = nextafter(max_j fl64(alpha_j / Q_j)).
+// Since c+ Q_j >= alpha_j the acceptance probability is alpha_j / (c+ Q_j) up to
+// the 2^-32 grid of u, so candidate-and-accept has probability proportional to
+// alpha_j whatever Q is: the law stays alpha_j / alpha_0.  After t_max rejected
+// trials the same fixed-point inverse transform as the uniform path runs.
+#include "launch.hpp"
+#include "select_core.hpp"
+
+namespace arsel {
+
+struct PropArgs {
+    const float *alpha;
+    const uint32_t *Q;
+    int64_t lda, ldq;
+    int32_t M, K;
+    uint64_t seed, step;
+    uint32_t t_max;
+    int32_t *index;
+    uint32_t *trials;
+};
+
+__device__ __forceinline__ double wave_max_f64(double x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t b = (uint64_t)__double_as_longlong(x);
+        const uint64_t o = shfl_xor_u64(b, off);
+        x = fmax(x, __longlong_as_double((long long)o));
+    }
+    return x;
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_select_proposal(PropArgs a)
+{
+    extern __shared__ uint32_t lds_u[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int k = blockIdx.x * NW + wave;
+    if (k >= a.K) return;
+    const uint32_t M = (uint32_t)a.M;
+    float *sa = reinterpret_cast<float *>(lds_u) + (size_t)wave * 3 * M;
+    uint32_t *sq = lds_u + (size_t)wave * 3 * M + M;
+    uint32_t *sp = sq + M;
+    const float *ga = a.alpha + (int64_t)k * a.lda;
+    const uint32_t *gq = a.Q + (int64_t)k * a.ldq;
+
+    // stage alpha and Q; validity, maximum, support coverage, sum Q, c
+    float amax = 0.0f;
+    bool bad = false, miss = false;
+    uint64_t sumq = 0;
+    double c = 0.0;
+    for (uint32_t j = lane; j < M; j += kWave) {
+        const float x = ga[j];
+        const uint32_t q = gq[j];
+        sa[j] = x;
+        sq[j] = q;
+        bad |= !(x >= 0.0f) | (x == __builtin_inff());
+        amax = fmaxf(amax, x);
+        if (x > 0.0f) {
+            if (q == 0)
+                miss = true;
+            else
+                c = fmax(c, (double)x / (double)q);
+        }
+        sumq += q;
+    }
+    bad = __ballot(bad) != 0;
+    miss = __ballot(miss) != 0;
+    amax = wave_max(amax);
+    sumq = wave_sum_u64(sumq);
+    c = wave_max_f64(c);
+    Outcome o;
+    o.trials = 0;
+    if (bad)
+        o.index = -2;
+    else if (amax == 0.0f)
+        o.index = -1;
+    else if (miss || sumq >= (1ull << 32))
+        o.index = -4;
+    else {
+        // inclusive prefix of Q (exact: sum Q < 2^32)
+        uint32_t carry = 0;
+        for (uint32_t base = 0; base < M; base += kWave) {
+            const uint32_t j = base + lane;
+            uint32_t v = j < M ? sq[j] : 0u;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_up((int)v, d, kWave);
+                if (lane >= d) v += y;
+            }
+            if (j < M) sp[j] = carry + v;
+            carry += readlane_u32(v, kWave - 1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t S = (uint32_t)sumq;
+        const uint32_t thresh = lemire_threshold(S);
+        const double cplus = __longlong_as_double(__double_as_longlong(c) + 1);   // nextafter up
+        const Stream st = make_stream(a.seed, a.step, (uint32_t)k, kTagProposal);
+        const uint32_t rounds = (uint32_t)(((uint64_t)a.t_max + kRoundTrials - 1) / kRoundTrials);
+        auto pick = [&](uint32_t V) {
+            uint32_t lo = 0, hi = M - 1;   // least j with P_j > V
+            while (lo < hi) {
+                const uint32_t mid = lo + ((hi - lo) >> 1);
+                if (sp[mid] > V)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            return lo;
+        };
+        auto accept = [&](uint32_t j, uint32_t uw) {
+            const double uc = grid_u(uw) * cplus;
+            return uc * (double)sq[j] < (double)sa[j];
+        };
+        uint64_t key = kNoAccept;
+        for (uint32_t r = 0; r < rounds && key == kNoAccept; r = uniform_u32(r + 1)) {
+            const uint64_t t0 = (uint64_t)r * kRoundTrials;
+            const Words w = st.block((uint32_t)(t0 >> 1) + (uint32_t)lane);
+            const uint64_t ta = t0 + 2 * (uint64_t)lane;
+            uint32_t va, vb;
+            const bool oka = lemire(w.w0, S, thresh, va) && ta < a.t_max;
+            const bool okb = lemire(w.w2, S, thresh, vb) && ta + 1 < a.t_max;
+            const uint32_t ja = pick(va), jb = pick(vb);
+            const bool acca = oka && accept(ja, w.w1);
+            const bool accb = okb && accept(jb, w.w3);
+            const uint64_t ma = __ballot(acca), mb = __ballot(accb);
+            if (ma | mb) {
+                const int la = first_lane(ma), lb = first_lane(mb);
+                key = la <= lb ? ((t0 + 2 * (uint64_t)la) << 32) | readlane_u32(ja, la)
+                               : ((t0 + 2 * (uint64_t)lb + 1) << 32) | readlane_u32(jb, lb);
+            }
+        }
+        if (key != kNoAccept) {
+            o.index = (int32_t)(uint32_t)key;
+            o.trials = (uint32_t)(key >> 32) + 1;
+        } else {
+            const int shift = 63 - ceil_log2_u32(M) - exponent_above(amax);
+            const ContigAcc acc{sa};
+            const uint64_t Sf = wave_fixed_sum(acc, M, shift);
+            const Words w = st.block(kFallbackBlock);
+            const uint64_t V = (uint64_t)w.w0 | ((uint64_t)w.w1 << 32);
+            o.index = wave_fixed_search(acc, M, shift, umul64hi(V, Sf));
+            o.trials = a.t_max + 1;
+        }
+    }
+    if (lane == 0) {
+        a.index[k] = o.index;
+        if (a.trials) a.trials[k] = o.trials;
+    }
+}
+
+}  // namespace arsel
+
+using namespace arsel;
+
+extern "C" int arsel_select_proposal(arsel_ctx *ctx, const float *alpha, const uint32_t *Q, int32_t M,
+                                     int32_t K, int64_t lda, int64_t ldq, uint64_t seed, uint64_t step,
+                                     uint32_t t_max, int32_t *index, uint32_t *trials, void *stream)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    if (M < 1 || K < 0) return ARSEL_ERR_SIZE;
+    if (lda < M || ldq < M) return ARSEL_ERR_LD;
+    if (K == 0) return ARSEL_OK;
+    if (!alpha || !Q || !index) return ARSEL_ERR_NULL;
+    int rc = ctx_activate(ctx);
+    if (rc) return rc;
+    const size_t per_wave = (size_t)3 * M * sizeof(uint32_t);
+    int nw = 4;
+    while (nw > 1 && per_wave * nw > ctx->tile_lds_bytes) nw >>= 1;
+    if (per_wave * nw > ctx->lds_per_block) return ARSEL_ERR_SIZE;
+    PropArgs a{alpha, Q, lda, ldq, M, K, seed, step, t_max, index, trials};
+    hipStream_t s = (hipStream_t)stream;
+    const int grid = (K + nw - 1) / nw;
+    switch (nw) {
+    case 4: hipLaunchKernelGGL(k_select_proposal<4>, dim3(grid), dim3(256), per_wave * 4, s, a); break;
+    case 2: hipLaunchKernelGGL(k_select_proposal<2>, dim3(grid), dim3(128), per_wave * 2, s, a); break;
+    default: hipLaunchKernelGGL(k_select_proposal<1>, dim3(grid), dim3(64), per_wave, s, a); break;
+    }
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}

@@ -1,0 +1,156 @@
+// Mass-action propensities and the SSA jump chain (training data for the
+// learned proposal).
+//
+// Reaction j of the network consumes species r0[j] (and r1[j] when >= 0) and
+// produces p0[j] (and p1[j] when >= 0).  Its propensity is
+// alpha_j = rate_j * fl32(h) with the combinatorial count h (int64): x_a for
+// one reactant, x_a x_b for two distinct ones, x_a (x_a - 1) / 2 for a
+// homodimer; fl32 rounds to nearest even.  The jump chain is the sequence of
+// states of the direct method (section "The Stochastic Simulation
+// Algorithm": select j, then X <- X + v_j); the holding times do not change
+// it, so they are not drawn.  Step i of realization r selects with uniform
+// acceptance-rejection on the tag-2 stream (instance r, step step0 + i).
+#include "launch.hpp"
+#include "select_core.hpp"
+
+namespace arsel {
+
+__device__ __forceinline__ float mass_action(const int32_t *x, int32_t a, int32_t b, float rate)
+{
+    int64_t h;
+    if (b < 0)
+        h = x[a];
+    else if (b == a)
+        h = (int64_t)x[a] * (x[a] - 1) / 2;
+    else
+        h = (int64_t)x[a] * x[b];
+    // nearest-even conversion of a non-negative count (h >= 0 for counts >= 0)
+    const float fh = h <= 0 ? 0.0f : fixed_to_float((uint64_t)h, 0);
+    return rate * fh;
+}
+
+struct NetArgs {
+    const int32_t *r0, *r1, *p0, *p1;
+    const float *rate;
+    int32_t N, M;
+};
+
+__global__ void k_propensities(NetArgs n, const int32_t *X, int32_t R, float *alpha)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)R * n.M) return;
+    const int64_t r = idx / n.M;
+    const int j = (int)(idx - r * n.M);
+    alpha[idx] = mass_action(X + r * n.N, n.r0[j], n.r1[j], n.rate[j]);
+}
+
+struct ChainArgs {
+    NetArgs net;
+    int32_t *X;          // [R][N], updated in place
+    int32_t R;
+    uint64_t seed, step0;
+    int64_t steps;
+    uint32_t t_max;
+    int64_t rec_from;
+    int32_t *rec_X;      // [(steps - rec_from)][R][N] or null
+    int32_t *fired;      // [steps][R] or null
+};
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront per realization: state and propensities in that wave's LDS.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_ssa_chain(ChainArgs c)
+{
+    extern __shared__ int32_t lds_i[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int r = blockIdx.x * NW + wave;
+    if (r >= c.R) return;
+    const int N = c.net.N, M = c.net.M;
+    int32_t *x = lds_i + (size_t)wave * (N + M);
+    float *a = reinterpret_cast<float *>(x + N);
+    int32_t *gx = c.X + (int64_t)r * N;
+    for (int i = lane; i < N; i += kWave) x[i] = gx[i];
+    wave_sync_lds();
+    for (int64_t i = 0; i < c.steps; ++i) {
+        if (c.rec_X && i >= c.rec_from) {
+            int32_t *dst = c.rec_X + ((i - c.rec_from) * c.R + r) * (int64_t)N;
+            for (int s = lane; s < N; s += kWave) dst[s] = x[s];
+        }
+        for (int j = lane; j < M; j += kWave)
+            a[j] = mass_action(x, c.net.r0[j], c.net.r1[j], c.net.rate[j]);
+        wave_sync_lds();
+        const Stream st = make_stream(c.seed, c.step0 + (uint64_t)i, (uint32_t)r, kTagSSA);
+        const Outcome o = wave_select(ContigAcc{a}, (uint32_t)M, nullptr, 0u, st, c.t_max, false);
+        const int32_t j = (int32_t)uniform_u32((uint32_t)o.index);
+        if (c.fired && lane == 0) c.fired[i * c.R + r] = j;
+        if (j >= 0 && lane == 0) {
+            x[c.net.r0[j]] -= 1;
+            if (c.net.r1[j] >= 0) x[c.net.r1[j]] -= 1;
+            x[c.net.p0[j]] += 1;
+            if (c.net.p1[j] >= 0) x[c.net.p1[j]] += 1;
+        }
+        wave_sync_lds();
+    }
+    for (int i = lane; i < N; i += kWave) gx[i] = x[i];
+}
+
+static int check_net(const arsel_network *n)
+{
+    if (!n || !n->r0 || !n->r1 || !n->p0 || !n->p1 || !n->rate) return ARSEL_ERR_NULL;
+    if (n->N < 1 || n->M < 1) return ARSEL_ERR_SIZE;
+    return ARSEL_OK;
+}
+
+static NetArgs net_args(const arsel_network *n)
+{
+    return NetArgs{n->r0, n->r1, n->p0, n->p1, n->rate, n->N, n->M};
+}
+
+}  // namespace arsel
+
+using namespace arsel;
+
+extern "C" int arsel_propensities(arsel_ctx *ctx, const arsel_network *net, const int32_t *X,
+                                  int32_t R, float *alpha, void *stream)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (R < 0) return ARSEL_ERR_SIZE;
+    if (R == 0) return ARSEL_OK;
+    if (!X || !alpha) return ARSEL_ERR_NULL;
+    if ((rc = ctx_activate(ctx))) return rc;
+    const int64_t n = (int64_t)R * net->M;
+    hipLaunchKernelGGL(k_propensities, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, net_args(net), X, R, alpha);
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
+
+extern "C" int arsel_ssa_chain(arsel_ctx *ctx, const arsel_network *net, int32_t *X, int32_t R,
+                               uint64_t seed, uint64_t step0, int64_t steps, uint32_t t_max,
+                               int64_t rec_from, int32_t *rec_X, int32_t *fired, void *stream)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (R < 0 || steps < 0 || rec_from < 0) return ARSEL_ERR_SIZE;
+    if (R == 0 || steps == 0) return ARSEL_OK;
+    if (!X) return ARSEL_ERR_NULL;
+    if ((rc = ctx_activate(ctx))) return rc;
+    const size_t per_wave = (size_t)(net->N + net->M) * 4;
+    if (per_wave > ctx->lds_per_block) return ARSEL_ERR_SIZE;
+    ChainArgs c{net_args(net), X, R, seed, step0, steps, t_max, rec_from, rec_X, fired};
+    hipStream_t s = (hipStream_t)stream;
+    if (per_wave * 4 <= ctx->tile_lds_bytes)
+        hipLaunchKernelGGL(k_ssa_chain<4>, dim3((R + 3) / 4), dim3(256), per_wave * 4, s, c);
+    else
+        hipLaunchKernelGGL(k_ssa_chain<1>, dim3(R), dim3(64), per_wave, s, c);
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
