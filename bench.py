@@ -38,7 +38,7 @@ def load_traffic(kernel: str):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_hash") != source_hash():
+    if rec.get("source_hash") != source_hash(kernel):
         return None
     return rec.get("bytes_per_launch")
 
@@ -61,6 +61,110 @@ def cpu_baseline(buf_host, threads: int, budget_s: float = 8.0):
                       f"sequential AR per instance, OpenMP over instances"}
 
 
+def bench_ragged(torch, arsel, workloads, reps: int = 20):
+    """Uneven batch: 10^4 instances, M log-uniform in [64, 65536], one
+    persistent launch with the autotuned schedule."""
+    from paper_1404_0027_amd import autotune
+
+    rb = workloads.ragged_mix(K=10000, seed=3)
+    a = torch.from_numpy(rb.alpha).cuda()
+    off = torch.from_numpy(rb.offsets).cuda()
+    tuned = autotune.tune_ragged(a, off, rb.offsets, reps=2, use_cache=False)
+    index = torch.empty(rb.K, dtype=torch.int32, device="cuda")
+    for s in range(3):
+        arsel.select_ragged(a, off, seed=SEED, step=s, host_offsets=rb.offsets, index=index)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for s in range(reps):
+        arsel.select_ragged(a, off, seed=SEED, step=s, host_offsets=rb.offsets, index=index)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    nbytes = 4 * int(rb.offsets[-1]) + 4 * rb.K
+    return {"workload": "10^4 instances, M = round(2^U(6,16)), families U(0,1]/Exp(1)/LN(0,3), "
+                        "ragged AoS, one persistent launch",
+            "instances_per_s": round(rb.K / (us * 1e-6), 1), "us_per_launch": round(us, 2),
+            "algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / (us * 1e-6) / 1e9, 1),
+            "frac_of_8TBs": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "schedule": dict(zip(("wave_max_m", "block_waves", "lds_max_m", "blocks_per_cu"),
+                                 tuned.schedule)),
+            "note": "includes the host-side longest-first ordering of each call"}
+
+
+def bench_learned(torch, np, arsel, workloads, epochs: int = 2):
+    """Learned proposal on the synthetic mass-action network (N=641, M=1029):
+    10^6 (state, propensity) pairs from GPU jump chains, training on the GPU,
+    then acceptance and selections/s against uniform AR on 4096 held-out
+    states."""
+    from paper_1404_0027_amd import learned
+
+    net = workloads.mass_action_network()
+    dn = learned.DeviceNetwork(net)
+    X0 = torch.from_numpy(workloads.poisson_counts(N=net.N, R=1000, seed=5)).cuda()
+    dn.chain(X0, seed=2, step0=0, steps=1000)
+    rec, _ = dn.chain(X0, seed=2, step0=1000, steps=1000, record_from=0)
+    X = rec.reshape(-1, net.N)
+    alpha = dn.propensities(X)
+    lp = learned.LearnedProposal(net.N, net.M, seed=0)
+    B = 1024
+    n = (X.shape[0] // B) * B
+    t0 = time.perf_counter()
+    for _ in range(epochs):
+        for s in range(0, n, B):
+            lp.train_step(X[s:s + B], alpha[s:s + B], lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    loss = float(lp.loss.item())
+    Xh = torch.from_numpy(workloads.poisson_counts(N=net.N, R=4096, seed=77)).cuda()
+    dn.chain(Xh, seed=9, step0=0, steps=500)
+    Ah = dn.propensities(Xh)
+    Q, _ = lp.forward(Xh, Ah)
+    idx = torch.empty(4096, dtype=torch.int32, device="cuda")
+    tr = torch.empty(4096, dtype=torch.int32, device="cuda")
+
+    def acc(trials):
+        t = trials.cpu().numpy().view(np.uint32).astype(np.int64)
+        ok = (t >= 1) & (t <= 4096)
+        return float(ok.sum() / (t[ok].sum() + 4096 * (t > 4096).sum()))
+
+    arsel.select(Ah, net.M, 4096, net.M, arsel.AOS, seed=SEED, index=idx, trials=tr)
+    acc_u = acc(tr)
+    arsel.select_proposal(Ah, Q, seed=SEED, index=idx, trials=tr)
+    acc_l = acc(tr)
+
+    def timed(fn, reps=200):
+        fn(0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for s in range(reps):
+            fn(s)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    t_u = timed(lambda s: arsel.select(Ah, net.M, 4096, net.M, arsel.AOS, seed=SEED, step=s,
+                                       index=idx))
+    t_p = timed(lambda s: arsel.select_proposal(Ah, Q, seed=SEED, step=s, index=idx))
+    def full(s):
+        lp.forward(Xh, Ah)
+        arsel.select_proposal(Ah, Q, seed=SEED, step=s, index=idx)
+
+    t_f = timed(full, reps=50)
+    return {"workload": "mass-action network N=641, M=1029, counts Poisson(50), R=4096 held-out "
+                        "states; MLP 641->256->256->1029 BF16 on MFMA",
+            "training": {"pairs": int(X.shape[0]), "epochs": epochs, "batch": B,
+                         "seconds": round(train_s, 2), "final_minibatch_loss": round(loss, 4)},
+            "acceptance_per_trial": {"uniform": round(acc_u, 5), "learned": round(acc_l, 5),
+                                     "gain": round(acc_l / acc_u, 2)},
+            "selections_per_s": {"uniform_AR": round(4096 / t_u, 1),
+                                 "learned_select_only": round(4096 / t_p, 1),
+                                 "learned_with_MLP_forward": round(4096 / t_f, 1)},
+            "note": "selections/s with the MLP forward include recomputing Q every call; the "
+                    "select-only rate applies when Q is reused across steps"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +173,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", type=int, default=0, help="dense tile override (results unchanged)")
     ap.add_argument("--waves", type=int, default=0, help="dense waves override (results unchanged)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the uneven-batch and learned-proposal measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -157,6 +263,15 @@ def main() -> int:
     if not args.no_cpu:
         cpu = cpu_baseline(host, threads=min(16, os.cpu_count() or 1))
 
+    ragged = learned_res = None
+    if not args.no_extras:
+        print("[bench] uneven batch", file=sys.stderr, flush=True)
+        ragged = bench_ragged(torch, arsel, workloads)
+        print("[bench] learned proposal", file=sys.stderr, flush=True)
+        learned_res = bench_learned(torch, np, arsel, workloads)
+        acceptance["learned_per_trial"] = learned_res["acceptance_per_trial"]["learned"]
+        acceptance["uniform_per_trial_same_states"] = learned_res["acceptance_per_trial"]["uniform"]
+
     out = {
         "metric": "next-reaction selections/sec at M=1029 (batched) + AR acceptance rate vs learned q",
         "value": round(sel_per_s, 1), "unit": "selections/s", "n_gpus": 1,
@@ -171,6 +286,8 @@ def main() -> int:
         "cpu_baseline": cpu,
         "acceptance": acceptance,
         "parity_last_step": parity,
+        "ragged": ragged,
+        "learned": learned_res,
     }
     print(json.dumps(out), flush=True)
     return 0 if parity == "ok" else 1

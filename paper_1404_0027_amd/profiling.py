@@ -29,9 +29,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_MIB = 64
 
 
-def source_hash() -> str:
+# sources each profiled kernel is compiled from (its traffic record is void
+# once any of them changes)
+KERNEL_SOURCES = {
+    "select_tile": ("select_dense.hip", "select_core.hpp", "device.hpp", "launch.hpp"),
+}
+
+
+def source_hash(kernel: str = "select_tile") -> str:
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    names = KERNEL_SOURCES.get(kernel)
+    paths = ([os.path.join(HERE, "csrc", n) for n in names] if names
+             else sorted(glob.glob(os.path.join(HERE, "csrc", "*"))))
+    for p in paths:
         with open(p, "rb") as f:
             h.update(os.path.basename(p).encode())
             h.update(f.read())
@@ -95,7 +105,7 @@ def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel, out_json) 
     write = _counter(write_db, kernel, "WRITE_SIZE") * w_factor * 1024.0
     rec = {"kernel": kernel, "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "bytes_per_launch": fetch + write, "fetch_calibration": f_factor,
-           "write_calibration": w_factor, "source_hash": source_hash()}
+           "write_calibration": w_factor, "source_hash": source_hash(kernel)}
     with open(out_json, "w") as f:
         json.dump(rec, f, indent=1)
     return rec
@@ -112,7 +122,7 @@ def main(argv: list[str]) -> int:
     elif argv[0] == "traffic":
         print(json.dumps(traffic(*argv[1:7])))
     elif argv[0] == "hash":
-        print(source_hash())
+        print(source_hash(*argv[1:2]))
     else:
         print(__doc__)
         return 2
