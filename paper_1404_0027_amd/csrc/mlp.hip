@@ -230,13 +230,33 @@ __global__ void k_softmax_quant(const float *Z, int64_t ldz, const float *alpha,
 }
 
 // Column sums of a [R][ld] FP32 matrix (bias gradients): out[n] = sum_r D[r][n].
-__global__ void k_colsum(const float *D, int64_t ld, int32_t R, int32_t N, float *out)
+// A workgroup owns 64 columns; its 16 row groups each sum rows g, g+16, ...
+// with four interleaved accumulators, then the partials are added in a fixed
+// order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(1024) void k_colsum(const float *D, int64_t ld, int32_t R, int32_t N,
+                                                 float *out)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    float s = 0.0f;
-    for (int r = 0; r < R; ++r) s += D[(int64_t)r * ld + n];
-    out[n] = s;
+    __shared__ float part[16][65];
+    const int c = threadIdx.x & 63;
+    const int g = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (n < N) {
+        int r = g;
+        for (; r + 48 < R; r += 64) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += D[(int64_t)(r + 16 * u) * ld + n];
+        }
+        for (int u = 0; r < R; r += 16, ++u) acc[u & 3] += D[(int64_t)r * ld + n];
+    }
+    part[g][c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (g == 0 && n < N) {
+        float s = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) s += part[i][c];
+        out[n] = s;
+    }
 }
 
 // Adam on FP32 master weights (bias-corrected), refreshing the BF16 copy.
@@ -406,7 +426,7 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
     g.C = tr->grad[4];
     g.ldc = n->H;
     if ((rc = gemm(g, false, false, s))) return rc;
-    hipLaunchKernelGGL(k_colsum, grid1(n->Mp), dim3(256), 0, s, dZf, (int64_t)n->Mp, B, n->Mp, tr->grad[5]);
+    hipLaunchKernelGGL(k_colsum, dim3((n->Mp + 63) / 64), dim3(1024), 0, s, dZf, (int64_t)n->Mp, B, n->Mp, tr->grad[5]);
     g = gemm_args(dZb, n->Mp, n->W3, n->H, B, n->H, n->Mp);              // dH2 = dZ W3 . [h2 > 0]
     g.mask = f.H2;
     g.ldm = n->H;
@@ -419,7 +439,7 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
     g.C = tr->grad[2];
     g.ldc = n->H;
     if ((rc = gemm(g, false, false, s))) return rc;
-    hipLaunchKernelGGL(k_colsum, grid1(n->H), dim3(256), 0, s, dH2f, (int64_t)n->H, B, n->H, tr->grad[3]);
+    hipLaunchKernelGGL(k_colsum, dim3((n->H + 63) / 64), dim3(1024), 0, s, dH2f, (int64_t)n->H, B, n->H, tr->grad[3]);
     g = gemm_args(dH2, n->H, n->W2, n->H, B, n->H, n->H);                // dH1 = dH2 W2 . [h1 > 0]
     g.mask = f.H1;
     g.ldm = n->H;
@@ -432,7 +452,7 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
     g.C = tr->grad[0];
     g.ldc = n->Kp;
     if ((rc = gemm(g, false, false, s))) return rc;
-    hipLaunchKernelGGL(k_colsum, grid1(n->H), dim3(256), 0, s, dH1f, (int64_t)n->H, B, n->H, tr->grad[1]);
+    hipLaunchKernelGGL(k_colsum, dim3((n->H + 63) / 64), dim3(1024), 0, s, dH1f, (int64_t)n->H, B, n->H, tr->grad[1]);
 
     const int64_t sizes[6] = {(int64_t)n->H * n->Kp, n->H, (int64_t)n->H * n->H, n->H,
                               (int64_t)n->Mp * n->H, n->Mp};

@@ -201,11 +201,11 @@ __device__ Outcome wave_fallback(const Acc &A, uint32_t M, bool scanned, float a
     return o;
 }
 
+// Rounds and fallback of one instance whose scan phase is done.
 template <class Acc>
-__device__ Outcome wave_select(const Acc &A, uint32_t M, const float *bound_k, uint32_t flags,
-                               const Stream &st, uint32_t t_max, bool want_alpha0)
+__device__ Outcome wave_run(const Acc &A, uint32_t M, const ScanState &s, const Stream &st,
+                            uint32_t t_max)
 {
-    const ScanState s = wave_prepare(A, M, bound_k, flags, want_alpha0);
     if (s.decided) return s.o;
     const uint32_t thresh = lemire_threshold(M);
     const double envd = (double)s.env;
@@ -220,6 +220,84 @@ __device__ Outcome wave_select(const Acc &A, uint32_t M, const float *bound_k, u
         }
     }
     return wave_fallback(A, M, s.scanned, s.amax, st, t_max, s.o.alpha0);
+}
+
+template <class Acc>
+__device__ Outcome wave_select(const Acc &A, uint32_t M, const float *bound_k, uint32_t flags,
+                               const Stream &st, uint32_t t_max, bool want_alpha0)
+{
+    return wave_run(A, M, wave_prepare(A, M, bound_k, flags, want_alpha0), st, t_max);
+}
+
+// As wave_select without a bound, given the bit-maximum of the instance taken
+// while it was loaded: below 0x7F800000 it certifies a valid vector and is
+// alpha_max itself, so the scan is skipped; otherwise the exact scan runs.
+template <class Acc>
+__device__ Outcome wave_select_hint(const Acc &A, uint32_t M, uint32_t maxbits, const Stream &st,
+                                    uint32_t t_max, bool want_alpha0)
+{
+    if (maxbits >= 0x7F800000u) return wave_select(A, M, nullptr, 0u, st, t_max, want_alpha0);
+    ScanState s;
+    s.scanned = true;
+    s.amax = __uint_as_float(maxbits);
+    s.decided = decide_status(true, false, s.amax, nullptr, 0u, s.env, s.o);
+    if (!s.decided && want_alpha0) {
+        const int shift = 63 - ceil_log2_u32(M) - exponent_above(s.amax);
+        s.o.alpha0 = fixed_to_float(wave_fixed_sum(A, M, shift), shift);
+    }
+    return wave_run(A, M, s, st, t_max);
+}
+
+// Stream n floats from src (4-byte aligned) with 16-byte loads, kStreamBatch
+// per thread in flight, copying them to dst (LDS) when dst is not null.
+// Thread tid of NT takes every NT-th slot.  Returns the thread's running
+// maximum of the raw bits (the certificate used by wave_select_hint).
+constexpr int kStreamBatch = 4;
+
+template <int NT>
+__device__ __forceinline__ uint32_t stream_bitmax(const float *src, uint32_t n, float *dst, int tid)
+{
+    uint32_t mb = 0;
+    const uint32_t align = (uint32_t)(((16 - ((uintptr_t)src & 15)) & 15) >> 2);
+    const uint32_t head = align < n ? align : n;
+    if ((uint32_t)tid < head) {
+        const float x = src[tid];
+        mb = __float_as_uint(x);
+        if (dst) dst[tid] = x;
+    }
+    const uint32_t nq = (n - head) >> 2;
+    const float *s4 = src + head;
+    for (uint32_t base = 0; base < nq; base += kStreamBatch * NT) {
+        f32x4 v[kStreamBatch];
+#pragma unroll
+        for (int u = 0; u < kStreamBatch; ++u) {
+            const uint32_t i = base + u * NT + tid;
+            if (i < nq) v[u] = load_stream4(s4 + 4 * i);
+        }
+#pragma unroll
+        for (int u = 0; u < kStreamBatch; ++u) {
+            const uint32_t i = base + u * NT + tid;
+            if (i < nq) {
+                mb = max(mb, __float_as_uint(v[u].x));
+                mb = max(mb, __float_as_uint(v[u].y));
+                mb = max(mb, __float_as_uint(v[u].z));
+                mb = max(mb, __float_as_uint(v[u].w));
+                if (dst) {
+                    float *d = dst + head + 4 * i;
+                    d[0] = v[u].x;
+                    d[1] = v[u].y;
+                    d[2] = v[u].z;
+                    d[3] = v[u].w;
+                }
+            }
+        }
+    }
+    for (uint32_t f = head + 4 * nq + tid; f < n; f += NT) {
+        const float x = src[f];
+        mb = max(mb, __float_as_uint(x));
+        if (dst) dst[f] = x;
+    }
+    return mb;
 }
 
 }  // namespace arsel

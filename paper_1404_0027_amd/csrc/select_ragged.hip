@@ -104,12 +104,7 @@ __global__ __launch_bounds__(NW * 64) void k_select_ragged(RaggedArgs a)
         const float *row = a.alpha + off;
         const bool staged = (int64_t)M <= (int64_t)a.lds_max_m;
         // one streaming pass: bit-maximum (validity + alpha_max), staging into LDS
-        uint32_t mb = 0;
-        for (uint32_t j = tid; j < M; j += NT) {
-            const float x = __builtin_nontemporal_load(row + j);
-            mb = max(mb, __float_as_uint(x));
-            if (staged) lds[j] = x;
-        }
+        uint32_t mb = stream_bitmax<NT>(row, M, staged ? lds : nullptr, tid);
         mb = block_max_u32<NW>(mb, bs);   // its barriers also publish the staged row
         const Stream st = make_stream(a.seed, a.step, (uint32_t)k, kTagUniform);
         const uint32_t hint = mb < 0x7F800000u ? mb : 0xFFFFFFFFu;
@@ -138,12 +133,12 @@ __global__ __launch_bounds__(NW * 64) void k_select_ragged(RaggedArgs a)
         } else {
             const uint32_t M = (uint32_t)m64;
             const float *row = a.alpha + off;
-            for (uint32_t j = lane; j < M; j += kWave) slice[j] = __builtin_nontemporal_load(row + j);
+            const uint32_t mb = wave_max_u32(stream_bitmax<kWave>(row, M, slice, lane));
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const Stream st = make_stream(a.seed, a.step, (uint32_t)k, kTagUniform);
-            o = wave_select(ContigAcc{slice}, M, nullptr, 0u, st, a.t_max, want_a0);
+            o = wave_select_hint(ContigAcc{slice}, M, mb, st, a.t_max, want_a0);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
