@@ -177,7 +177,7 @@ __device__ __forceinline__ bool stage_tile(const DenseArgs &a, float *lds, int k
 }
 
 // Rounds whose random draws are computed while the tile streams in.
-constexpr int kPreRounds = 3;
+constexpr int kPreRounds = 4;
 constexpr uint32_t kNoCand = 0xFFFFFFFFu;
 
 // The two trials of one lane in one round: candidates (kNoCand when the
@@ -222,7 +222,6 @@ struct TileState {
     uint64_t best[kMaxTile];      // least accepted (trial << 32 | j) so far
     uint64_t open;                // instances whose rounds are still handed out
     uint32_t next[kMaxTile];      // next round to hand out
-    uint32_t inflight[kMaxTile];  // rounds of the instance being run now
     double env[kMaxTile];
     float amax[kMaxTile];
     float alpha0[kMaxTile];
@@ -306,6 +305,8 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
         uint32_t r = 0;
         if (!sc.decided) {
             const double envd = (double)sc.env;
+            // instances beyond the first NW of a tile start at round 0 in the
+            // batches below
             if (t == wave) {
 #pragma unroll
                 for (int rr = 0; rr < kPreRounds; ++rr) {
@@ -314,10 +315,6 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
                         r = rr + 1;
                     }
                 }
-            } else {
-                const Stream st = make_stream(a.seed, a.step, (uint32_t)k, kTagUniform);
-                for (; r < (uint32_t)kPreRounds && r < rounds && key == kNoAccept; ++r)
-                    key = resolve_round(acc, lane_draw(st, r, M, thresh, a.t_max), envd, r);
             }
         }
         if (sc.decided || key != kNoAccept) {
@@ -337,71 +334,45 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
             ts.env[t] = (double)sc.env;
             ts.best[t] = key;
             ts.next[t] = r;
-            ts.inflight[t] = 0;
             if (!sc.decided && key == kNoAccept && r < rounds)
                 atomicOr((unsigned long long *)&ts.open, 1ull << t);
         }
     }
     __syncthreads();
 
-    // Remaining rounds (rare): handed out per instance in increasing order (an
-    // LDS counter) to any wave; the least accepted trial is kept with a 64-bit
-    // atomic minimum, so the result is the sequential rule's whatever the
-    // schedule.  At most NW / (open instances) rounds of one instance run at
-    // once: no speculative rounds while many instances are open, all waves on
-    // the last ones.
-    if (uniform_u64(ts.open) != 0) {
-        int t = nk > 0 ? wave % nk : 0;
-        for (;;) {
-            const uint64_t open = uniform_u64(
-                __hip_atomic_load(&ts.open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-            if (open == 0) break;
-            const int cnt = __popcll(open);
-            const uint32_t limit = (uint32_t)max(1, NW / cnt);
-            uint64_t rest = open;
-            bool found = false;
-            for (int c = 0; c < cnt && !found; ++c) {
-                const uint64_t hi = rest & (~0ull << t);
-                const int cand = (int)__builtin_ctzll(hi ? hi : rest);
-                const uint32_t inf = uniform_u32(__hip_atomic_load(&ts.inflight[cand], __ATOMIC_RELAXED,
-                                                                   __HIP_MEMORY_SCOPE_WORKGROUP));
-                if (inf < limit) {
-                    t = cand;
-                    found = true;
-                } else {
-                    rest &= ~(1ull << cand);
-                    if (!rest) break;
-                }
-            }
-            if (!found) {
-                __builtin_amdgcn_s_sleep(2);
-                continue;
-            }
-            wave_fetch_add(&ts.inflight[t], 1u);
-            const uint32_t r = wave_fetch_add(&ts.next[t], 1u);
-            const uint64_t bk = uniform_u64(
-                __hip_atomic_load(&ts.best[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-            if (r >= rounds || (bk >> 32) < (uint64_t)r * kRoundTrials) {
-                if (lane == 0) {
-                    atomicAnd((unsigned long long *)&ts.open, ~(1ull << t));
-                    atomicSub(&ts.inflight[t], 1u);
-                }
-                continue;
-            }
+    // Remaining rounds, in batches: the open instances (at most NW per batch)
+    // share the NW waves round-robin, instance i of the batch running rounds
+    // next .. next + n_i - 1 at once.  A barrier ends the batch; an instance
+    // whose batch accepted closes with the least accepted trial (every lower
+    // round was run in an earlier batch and rejected), so the result is the
+    // sequential rule's.
+    for (;;) {
+        const uint64_t open = uniform_u64(ts.open);
+        if (open == 0) break;
+        const int cnt = __popcll(open);
+        const int slots = cnt < NW ? cnt : NW;
+        const int i = wave % slots;
+        uint64_t m = open;
+        for (int c = 0; c < i; ++c) m &= m - 1;
+        const int t = (int)__builtin_ctzll(m);
+        const uint32_t base = uniform_u32(ts.next[t]);
+        const uint32_t r = base + (uint32_t)(wave / slots);
+        if (r < rounds) {
             const Stream st = make_stream(a.seed, a.step, (uint32_t)(k0 + t), kTagUniform);
             const ContigAcc acc{lds + (bcast ? 0 : t * a.mp)};
             const uint64_t key = resolve_round(acc, lane_draw(st, r, M, thresh, a.t_max), ts.env[t], r);
-            if (lane == 0) {
-                if (key != kNoAccept) {
-                    atomicMin((unsigned long long *)&ts.best[t], (unsigned long long)key);
-                    // every round below r has been handed out; no later round can win
-                    atomicAnd((unsigned long long *)&ts.open, ~(1ull << t));
-                }
-                atomicSub(&ts.inflight[t], 1u);
-            }
+            if (key != kNoAccept && lane == 0)
+                atomicMin((unsigned long long *)&ts.best[t], (unsigned long long)key);
         }
+        __syncthreads();
+        if (wave == i && lane == 0) {
+            const uint32_t n = (uint32_t)((NW - i + slots - 1) / slots);
+            ts.next[t] = base + n;
+            if (ts.best[t] != kNoAccept || base + n >= rounds)
+                atomicAnd((unsigned long long *)&ts.open, ~(1ull << t));
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     // Finish: fallback where every round rejected, then write.
     for (int tt = wave; tt < nk; tt += NW) {
