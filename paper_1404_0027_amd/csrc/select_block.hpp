@@ -80,17 +80,19 @@ __device__ void block_scan(const Acc &A, uint32_t M, float &amax, bool &bad, Blo
     amax = __uint_as_float(mb);
 }
 
-// Exact fixed-point inverse transform over the block: thread i owns the
-// contiguous range [i L, (i + 1) L); range sums are read in a skewed order
-// (the sum does not depend on it) so that LDS lanes do not share a bank.
+// Least j in [0, n) whose inclusive prefix of F_j = floor(alpha_j 2^shift)
+// exceeds target, or -1 when the n elements sum to at most target.  Thread i
+// owns the contiguous range [i L, (i + 1) L); range sums are read in a skewed
+// order (the sum does not depend on it) so that LDS lanes do not share a bank.
+// `total` returns the sum of the n weights.
 template <int NW, class Acc>
-__device__ int32_t block_fallback_pick(const Acc &A, uint32_t M, int shift, const Stream &st,
-                                       BlockScratch<NW> &bs)
+__device__ int32_t block_prefix_search(const Acc &A, uint32_t n_all, int shift, uint64_t target,
+                                       uint64_t &total, BlockScratch<NW> &bs)
 {
     constexpr int NT = NW * kWave;
     const uint32_t tid = threadIdx.x;
-    const uint32_t L = (M + NT - 1) / NT;
-    const uint32_t lo = min(tid * L, M), hi = min(lo + L, M);
+    const uint32_t L = (n_all + NT - 1) / NT;
+    const uint32_t lo = min(tid * L, n_all), hi = min(lo + L, n_all);
     const uint32_t n = hi - lo;
     uint64_t part = 0;
     uint32_t idx = n ? tid % n : 0;
@@ -100,9 +102,7 @@ __device__ int32_t block_fallback_pick(const Acc &A, uint32_t M, int shift, cons
     }
     uint64_t S = 0;
     const uint64_t before = block_excl_scan_u64<NW>(part, S, bs);
-    const Words w = st.block(kFallbackBlock);
-    const uint64_t V = (uint64_t)w.w0 | ((uint64_t)w.w1 << 32);
-    const uint64_t target = umul64hi(V, S);
+    total = S;
     if (tid == 0) bs.found = -1;
     __syncthreads();
     if (n > 0 && before <= target && target < before + part) {
@@ -121,12 +121,59 @@ __device__ int32_t block_fallback_pick(const Acc &A, uint32_t M, int shift, cons
     return j;
 }
 
+// Exact fixed-point inverse transform over the block (instance resident in
+// LDS, or any accessor for moderate M).
+template <int NW, class Acc>
+__device__ int32_t block_fallback_pick(const Acc &A, uint32_t M, int shift, const Stream &st,
+                                       BlockScratch<NW> &bs)
+{
+    // S first (the target depends on it), then the search.
+    uint64_t S = 0;
+    for (uint32_t j = threadIdx.x; j < M; j += NW * kWave) S += fixed_weight(A(j), shift);
+    S = block_sum_u64<NW>(S, bs);
+    const Words w = st.block(kFallbackBlock);
+    const uint64_t V = (uint64_t)w.w0 | ((uint64_t)w.w1 << 32);
+    uint64_t tot;
+    return block_prefix_search<NW>(A, M, shift, umul64hi(V, S), tot, bs);
+}
+
+// The same for an instance left in global memory: one streaming pass for S,
+// then the row is copied into LDS piece by piece (coalesced, several loads in
+// flight) until the piece holding the target is found and searched there.
+template <int NW>
+__device__ int32_t block_fallback_global(const float *row, uint32_t M, int shift, const Stream &st,
+                                         float *piece_buf, uint32_t piece, BlockScratch<NW> &bs)
+{
+    constexpr int NT = NW * kWave;
+    const uint64_t S = block_sum_u64<NW>(stream_fixed_sum<NT>(row, M, shift, threadIdx.x), bs);
+    const Words w = st.block(kFallbackBlock);
+    const uint64_t V = (uint64_t)w.w0 | ((uint64_t)w.w1 << 32);
+    const uint64_t target = umul64hi(V, S);
+    uint64_t before = 0;
+    for (uint32_t p0 = 0; p0 < M; p0 += piece) {
+        const uint32_t n = min(piece, M - p0);
+        stream_each<NT>(row + p0, n, threadIdx.x, [&](uint32_t j, float x) { piece_buf[j] = x; });
+        __syncthreads();
+        uint64_t part;
+        const int32_t j = block_prefix_search<NW>(ContigAcc{piece_buf}, n, shift, target - before, part, bs);
+        if (j >= 0) return (int32_t)p0 + j;
+        before += part;
+    }
+    return -1;   // unreachable for S > 0
+}
+
 // The whole selection for one instance.  maxbits_hint: the block-wide bit
 // maximum from a fused load pass (certifies validity when < 0x7F800000), or
 // 0xFFFFFFFF when no such pass ran.
+//
+// global_row: the instance's row in global memory when A reads it there (no
+// LDS copy); its fallback and alpha0 passes then stream the row and stage it
+// piece by piece in piece_buf (piece floats).  Null when A reads LDS.
 template <int NW, class Acc>
 __device__ Outcome block_select(const Acc &A, uint32_t M, uint32_t maxbits_hint, const Stream &st,
-                                uint32_t t_max, bool want_alpha0, BlockScratch<NW> &bs)
+                                uint32_t t_max, bool want_alpha0, BlockScratch<NW> &bs,
+                                const float *global_row = nullptr, float *piece_buf = nullptr,
+                                uint32_t piece = 0)
 {
     const int wave = threadIdx.x >> 6;
     float amax;
@@ -144,7 +191,10 @@ __device__ Outcome block_select(const Acc &A, uint32_t M, uint32_t maxbits_hint,
     const int shift = 63 - L - exponent_above(amax);
     if (want_alpha0) {
         uint64_t s = 0;
-        for (uint32_t j = threadIdx.x; j < M; j += NW * kWave) s += fixed_weight(A(j), shift);
+        if (global_row)
+            s = stream_fixed_sum<NW * kWave>(global_row, M, shift, threadIdx.x);
+        else
+            for (uint32_t j = threadIdx.x; j < M; j += NW * kWave) s += fixed_weight(A(j), shift);
         o.alpha0 = fixed_to_float(block_sum_u64<NW>(s, bs), shift);
     }
     const uint32_t thresh = lemire_threshold(M);
@@ -168,7 +218,10 @@ __device__ Outcome block_select(const Acc &A, uint32_t M, uint32_t maxbits_hint,
             return o;
         }
     }
-    o.index = block_fallback_pick<NW>(A, M, shift, st, bs);
+    if (global_row && piece_buf && piece > 0)
+        o.index = block_fallback_global<NW>(global_row, M, shift, st, piece_buf, piece, bs);
+    else
+        o.index = block_fallback_pick<NW>(A, M, shift, st, bs);
     o.trials = t_max + 1;
     return o;
 }

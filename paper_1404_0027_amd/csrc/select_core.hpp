@@ -249,22 +249,16 @@ __device__ Outcome wave_select_hint(const Acc &A, uint32_t M, uint32_t maxbits, 
 }
 
 // Stream n floats from src (4-byte aligned) with 16-byte loads, kStreamBatch
-// per thread in flight, copying them to dst (LDS) when dst is not null.
-// Thread tid of NT takes every NT-th slot.  Returns the thread's running
-// maximum of the raw bits (the certificate used by wave_select_hint).
-constexpr int kStreamBatch = 4;
+// per thread in flight; thread tid of NT takes every NT-th slot and calls
+// f(j, alpha_j) for each element it loads (any order).
+constexpr int kStreamBatch = 8;
 
-template <int NT>
-__device__ __forceinline__ uint32_t stream_bitmax(const float *src, uint32_t n, float *dst, int tid)
+template <int NT, class F>
+__device__ __forceinline__ void stream_each(const float *src, uint32_t n, int tid, F &&f)
 {
-    uint32_t mb = 0;
     const uint32_t align = (uint32_t)(((16 - ((uintptr_t)src & 15)) & 15) >> 2);
     const uint32_t head = align < n ? align : n;
-    if ((uint32_t)tid < head) {
-        const float x = src[tid];
-        mb = __float_as_uint(x);
-        if (dst) dst[tid] = x;
-    }
+    if ((uint32_t)tid < head) f((uint32_t)tid, src[tid]);
     const uint32_t nq = (n - head) >> 2;
     const float *s4 = src + head;
     for (uint32_t base = 0; base < nq; base += kStreamBatch * NT) {
@@ -278,26 +272,41 @@ __device__ __forceinline__ uint32_t stream_bitmax(const float *src, uint32_t n, 
         for (int u = 0; u < kStreamBatch; ++u) {
             const uint32_t i = base + u * NT + tid;
             if (i < nq) {
-                mb = max(mb, __float_as_uint(v[u].x));
-                mb = max(mb, __float_as_uint(v[u].y));
-                mb = max(mb, __float_as_uint(v[u].z));
-                mb = max(mb, __float_as_uint(v[u].w));
-                if (dst) {
-                    float *d = dst + head + 4 * i;
-                    d[0] = v[u].x;
-                    d[1] = v[u].y;
-                    d[2] = v[u].z;
-                    d[3] = v[u].w;
-                }
+                const uint32_t j = head + 4 * i;
+                f(j, v[u].x);
+                f(j + 1, v[u].y);
+                f(j + 2, v[u].z);
+                f(j + 3, v[u].w);
             }
         }
     }
-    for (uint32_t f = head + 4 * nq + tid; f < n; f += NT) {
-        const float x = src[f];
-        mb = max(mb, __float_as_uint(x));
-        if (dst) dst[f] = x;
-    }
+    for (uint32_t j = head + 4 * nq + tid; j < n; j += NT) f(j, src[j]);
+}
+
+// Streaming pass that copies the elements to dst (LDS) when dst is not null
+// and returns the thread's running maximum of the raw bits (the certificate
+// used by wave_select_hint).
+template <int NT>
+__device__ __forceinline__ uint32_t stream_bitmax(const float *src, uint32_t n, float *dst, int tid)
+{
+    uint32_t mb = 0;
+    if (dst)
+        stream_each<NT>(src, n, tid, [&](uint32_t j, float x) {
+            mb = max(mb, __float_as_uint(x));
+            dst[j] = x;
+        });
+    else
+        stream_each<NT>(src, n, tid, [&](uint32_t j, float x) { mb = max(mb, __float_as_uint(x)); });
     return mb;
+}
+
+// The thread's part of sum_j floor(alpha_j 2^shift) over a global row.
+template <int NT>
+__device__ __forceinline__ uint64_t stream_fixed_sum(const float *src, uint32_t n, int shift, int tid)
+{
+    uint64_t s = 0;
+    stream_each<NT>(src, n, tid, [&](uint32_t, float x) { s += fixed_weight(x, shift); });
+    return s;
 }
 
 }  // namespace arsel

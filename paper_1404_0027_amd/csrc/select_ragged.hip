@@ -6,8 +6,8 @@
 // gathered from global memory right after the streaming pass that computes
 // the maximum), small ones by a single wavefront.  Persistent workgroups
 // take items from the two lists through atomic counters, the large list
-// first; with host-side sizes both lists are ordered longest first.  The
-// schedule (wave_max_m, waves per workgroup, lds_max_m, workgroups per CU) is
+// first; with host-side sizes both lists are ordered longest first (by
+// power-of-two size class).  The schedule (wave_max_m, waves per workgroup, lds_max_m, workgroups per CU) is
 // chosen by the autotuner and never changes the results: every instance
 // gets the same trial stream and rule as arsel_select with instance id k.
 #include <algorithm>
@@ -80,13 +80,16 @@ __global__ __launch_bounds__(NW * 64) void k_select_ragged(RaggedArgs a)
     const uint32_t n_wave = uniform_u32(a.counts ? a.counts[1] : a.n_wave);
     const bool want_a0 = a.alpha0 != nullptr;
 
-    // Large instances: the whole workgroup per instance.
+    // Large instances: the whole workgroup per instance.  The next item is
+    // claimed as soon as the current one starts (the atomic's latency then
+    // overlaps the current item) and published through LDS at its end.
+    if (tid == 0) item = atomicAdd(&a.queue[0], 1u);
     for (;;) {
-        if (tid == 0) item = atomicAdd(&a.queue[0], 1u);
         __syncthreads();
         const uint32_t i = uniform_u32(item);
         __syncthreads();
         if (i >= n_block) break;
+        const uint32_t claimed = tid == 0 ? atomicAdd(&a.queue[0], 1u) : 0u;
         const int k = a.list_block[i];
         const int64_t off = a.offsets[k];
         const int64_t m64 = a.offsets[k + 1] - off;
@@ -97,6 +100,7 @@ __global__ __launch_bounds__(NW * 64) void k_select_ragged(RaggedArgs a)
                 o.alpha0 = m64 == 0 ? 0.0f : __builtin_nanf("");
                 o.trials = 0;
                 ragged_write(a, k, o);
+                item = claimed;
             }
             continue;
         }
@@ -112,16 +116,23 @@ __global__ __launch_bounds__(NW * 64) void k_select_ragged(RaggedArgs a)
         if (staged)
             o = block_select<NW>(ContigAcc{lds}, M, hint, st, a.t_max, want_a0, bs);
         else
-            o = block_select<NW>(ContigAcc{row}, M, hint, st, a.t_max, want_a0, bs);
-        if (tid == 0) ragged_write(a, k, o);
-        __syncthreads();
+            o = block_select<NW>(ContigAcc{row}, M, hint, st, a.t_max, want_a0, bs, row, lds,
+                                 (uint32_t)max(a.lds_max_m, NW * a.wave_max_m));
+        if (tid == 0) {
+            ragged_write(a, k, o);
+            item = claimed;
+        }
     }
 
     // Small instances: one wavefront per instance, staged in the wave's LDS slice.
     float *slice = lds + (size_t)wave * a.wave_max_m;
+    // Same prefetch of the next item, per wavefront: the claim's old value
+    // stays in a register until the current item is done.
+    uint32_t claim = atomicAdd(&a.queue[1], lane == 0 ? 1u : 0u);
     for (;;) {
-        const uint32_t i = wave_fetch_add(&a.queue[1], 1u);
+        const uint32_t i = uniform_u32(claim);
         if (i >= n_wave) break;
+        claim = atomicAdd(&a.queue[1], lane == 0 ? 1u : 0u);
         const int k = a.list_wave[i];
         const int64_t off = a.offsets[k];
         const int64_t m64 = a.offsets[k + 1] - off;
@@ -210,15 +221,26 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
     if (host_sizes) {
         // Longest first within each list; the lists go to the device through a
         // pinned staging buffer (reused once the previous copy has finished).
+        // Counting sort on floor(log2 M) (O(K)): sizes within a factor 2 keep
+        // their order, larger buckets first.
+        auto bucket = [&](int32_t k) {
+            const int64_t m = host_sizes[k];
+            return m <= 1 ? 0 : 63 - __builtin_clzll((unsigned long long)m);
+        };
+        size_t nb[64] = {0};
+        for (int32_t k = 0; k < K; ++k) ++nb[bucket(k)];
+        size_t start[64];
+        size_t acc = 0;
+        for (int b = 63; b >= 0; --b) {
+            start[b] = acc;
+            acc += nb[b];
+        }
+        std::vector<int32_t> order(K);
+        for (int32_t k = 0; k < K; ++k) order[start[bucket(k)]++] = k;
         std::vector<int32_t> blk, wav;
         blk.reserve(K);
         wav.reserve(K);
-        for (int32_t k = 0; k < K; ++k) (host_sizes[k] > sc.wave_max_m ? blk : wav).push_back(k);
-        auto longer = [&](int32_t x, int32_t y) {
-            return host_sizes[x] != host_sizes[y] ? host_sizes[x] > host_sizes[y] : x < y;
-        };
-        std::sort(blk.begin(), blk.end(), longer);
-        std::sort(wav.begin(), wav.end(), longer);
+        for (int32_t k : order) (host_sizes[k] > sc.wave_max_m ? blk : wav).push_back(k);
         const size_t bytes = 2 * (size_t)K * sizeof(int32_t);
         if (ctx->staging_event && hipEventSynchronize(ctx->staging_event) != hipSuccess)
             return ARSEL_ERR_HIP;

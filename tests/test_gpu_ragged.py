@@ -67,6 +67,18 @@ def test_ragged_fallbacks(gpu, t_max):
         assert np.all((g[2] <= 2) | (g[0] < 0)) and np.any(g[2] == 2)
 
 
+@pytest.mark.parametrize("sched", [(64, 8, 0, 2), (256, 4, 2048, 1)])
+def test_ragged_global_fallback_in_pieces(gpu, restore_schedule, sched):
+    """Instances left in global memory take the fallback by staging the row
+    piece by piece (pieces of max(lds_max_m, waves x wave_max_m) floats, so
+    many pieces per instance here); alpha0 is streamed from global memory."""
+    arsel.set_schedule(arsel.Schedule(*sched))
+    rb = workloads.ragged_mix(K=60, seed=8, log2_lo=10, log2_hi=16)
+    for t_max in (0, 3):
+        g, o = _ragged_both(rb.alpha, rb.offsets, seed=6, step=t_max, t_max=t_max)
+        assert_same(g, o, f"schedule {sched} t_max {t_max}")
+
+
 def test_ragged_edge_instances(gpu):
     rng = np.random.default_rng(7)
     rows = [np.zeros(0), np.zeros(5), np.array([2.0]), rng.random(3000),
