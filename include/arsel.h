@@ -82,7 +82,8 @@ const char *arsel_strerror(int code);
  * Dense batch: K instances with M reactions each (section "Results /
  * Implementation": propensities of realization k stored as D[k*M + j]).
  *   layout ARSEL_AOS: alpha[k*ld + j]; ld == 0 broadcasts one vector to all K
- *                     instances; otherwise ld >= M.
+ *                     instances (packed rounds, see arsel_set_trial_lanes);
+ *                     otherwise ld >= M.
  *   layout ARSEL_SOA: alpha[j*ld + k], ld >= K (coalesced across instances).
  *   bound:   NULL -> alpha_max is computed per instance (exact maximum);
  *            else K per-instance bounds B_k >= max_j alpha_j used in place of
@@ -106,6 +107,17 @@ int arsel_select(arsel_ctx *ctx, const float *alpha, int32_t M, int32_t K, int64
 /* Dense-path schedule: at most `tile` instances per workgroup tile (1..64)
  * and `waves` wavefronts per workgroup (4, 8 or 16).  Results never change. */
 int arsel_set_dense_config(arsel_ctx *ctx, int32_t tile, int32_t waves);
+
+/*
+ * Trial width of the broadcast kernels (arsel_select with ARSEL_AOS, ld == 0
+ * and no bound; arsel_select_proposal with lda == ldq == 0): the vector is
+ * staged once per workgroup and each wavefront serves 64 / lanes instances at
+ * a time, `lanes` lanes (2 * lanes trials) per instance per round.  lanes is
+ * 0 (chosen per launch from the acceptance rate and K) or a power of two in
+ * 1..64; ARSEL_ERR_ARG otherwise.  Results never change: trial t of instance
+ * k is the same trial for every width and the first accepted one wins.
+ */
+int arsel_set_trial_lanes(arsel_ctx *ctx, int32_t lanes);
 
 /*
  * Uneven batch in one persistent launch: instance k has
@@ -153,8 +165,10 @@ int arsel_set_schedule(arsel_ctx *ctx, const arsel_schedule *s);
  * so the law is alpha_j / alpha_0 for any Q; after t_max rejected trials the
  * same fixed-point inverse transform as arsel_select runs.  index: -4 when
  * Q_j = 0 for some alpha_j > 0, or sum Q >= 2^32 (after the -2 / -1 checks).
- * M up to ~13000 (alpha, Q and the prefix of one instance live in LDS);
- * ARSEL_ERR_SIZE beyond.
+ * lda == 0 (ldq == 0) gives every instance the same alpha (Q); otherwise
+ * lda, ldq >= M (ARSEL_ERR_LD).  With both 0 the broadcast kernel with packed
+ * rounds runs (see arsel_set_trial_lanes).  M up to ~13000 (alpha, Q and the
+ * prefix of one instance live in LDS); ARSEL_ERR_SIZE beyond.
  */
 int arsel_select_proposal(arsel_ctx *ctx, const float *alpha, const uint32_t *Q, int32_t M,
                           int32_t K, int64_t lda, int64_t ldq, uint64_t seed, uint64_t step,

@@ -138,6 +138,22 @@ def select_proposal(alpha: np.ndarray, Q: np.ndarray, *, seed: int, step: int = 
     return idx, tr
 
 
+def select_proposal_broadcast(alpha: np.ndarray, Q: np.ndarray, K: int, *, seed: int,
+                              step: int = 0, t_max: int = 4096, threads: int = 1):
+    """K instances sharing one alpha [M] and one Q [M] (instance k keeps its
+    own stream).  Returns (index, trials)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float32).ravel()
+    q = np.ascontiguousarray(Q, dtype=np.uint32).ravel()
+    M = a.shape[0]
+    idx = np.empty(K, dtype=np.int32)
+    tr = np.empty(K, dtype=np.uint32)
+    rc = lib().orc_select_proposal(_p(a), _p(q), M, K, 0, 0, seed, step, t_max, _p(idx),
+                                   _p(tr), threads)
+    if rc != 0:
+        raise ValueError("orc_select_proposal rejected its arguments")
+    return idx, tr
+
+
 def propensities(net, X: np.ndarray) -> np.ndarray:
     """Mass-action propensities alpha[r, j] of states X[r, i] (int32)."""
     x = np.ascontiguousarray(X, dtype=np.int32)

@@ -101,6 +101,7 @@ _EXTRA_SIGNATURES = {
     "arsel_get_schedule": [_P, ctypes.POINTER(Schedule)],
     "arsel_set_schedule": [_P, ctypes.POINTER(Schedule)],
     "arsel_set_dense_config": [_P, ctypes.c_int32, ctypes.c_int32],
+    "arsel_set_trial_lanes": [_P, ctypes.c_int32],
 }
 
 
@@ -196,6 +197,12 @@ def set_dense_config(tile: int, waves: int, device=None) -> None:
     _check(lib().arsel_set_dense_config(context(device), tile, waves), "arsel_set_dense_config")
 
 
+def set_trial_lanes(lanes: int, device=None) -> None:
+    """Lanes per instance of the broadcast kernels (0: automatic; else a power
+    of two in 1..64).  Results unchanged."""
+    _check(lib().arsel_set_trial_lanes(context(device), lanes), "arsel_set_trial_lanes")
+
+
 def get_schedule(device=None) -> Schedule:
     s = Schedule()
     _check(lib().arsel_get_schedule(context(device), ctypes.byref(s)), "arsel_get_schedule")
@@ -277,6 +284,33 @@ def select_proposal(alpha: torch.Tensor, Q: torch.Tensor, *, seed: int, step: in
     if trials is not None:
         _need(trials, torch.int32, K, "trials", dev)
     rc = lib().arsel_select_proposal(context(dev), _ptr(alpha), _ptr(Q), M, K, M, M,
+                                     seed & (2**64 - 1), step & (2**64 - 1), t_max, _ptr(index),
+                                     _ptr(trials), _stream(dev))
+    _check(rc, "arsel_select_proposal")
+    return index, trials
+
+
+def select_proposal_broadcast(alpha: torch.Tensor, Q: torch.Tensor, K: int, *, seed: int,
+                              step: int = 0, t_max: int = 4096, want_trials: bool = False,
+                              index: torch.Tensor | None = None,
+                              trials: torch.Tensor | None = None):
+    """K selections from ONE (alpha [M], Q [M]) pair (arsel_select_proposal with
+    lda = ldq = 0): instance k uses the tag-1 stream of instance id k."""
+    M = alpha.numel()
+    dev = alpha.device
+    _need(alpha, torch.float32, M, "alpha", dev)
+    if Q.dtype not in (torch.int32, torch.uint32) or Q.numel() != M:
+        raise ArselError("Q must hold M 32-bit integers")
+    if not Q.is_contiguous() or Q.device != dev:
+        raise ArselError("Q must be contiguous on the same GPU")
+    if index is None:
+        index = torch.empty(K, dtype=torch.int32, device=dev)
+    _need(index, torch.int32, K, "index", dev)
+    if want_trials and trials is None:
+        trials = torch.empty(K, dtype=torch.int32, device=dev)
+    if trials is not None:
+        _need(trials, torch.int32, K, "trials", dev)
+    rc = lib().arsel_select_proposal(context(dev), _ptr(alpha), _ptr(Q), M, K, 0, 0,
                                      seed & (2**64 - 1), step & (2**64 - 1), t_max, _ptr(index),
                                      _ptr(trials), _stream(dev))
     _check(rc, "arsel_select_proposal")

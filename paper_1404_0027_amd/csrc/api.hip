@@ -27,6 +27,7 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     c->tile_lds_bytes = std::min<size_t>(c->lds_per_block, 80 * 1024);
     c->dense_tile = 16;
     c->dense_waves = 16;
+    c->trial_lanes = 0;
     c->sched.wave_max_m = 1024;
     c->sched.block_waves = 8;
     c->sched.lds_max_m = 8192;

@@ -15,6 +15,7 @@ struct arsel_ctx {
     size_t tile_lds_bytes;    // LDS budget of one dense tile
     int dense_tile;           // instances per dense tile (upper bound)
     int dense_waves;          // wavefronts per dense workgroup (4, 8, 16)
+    int trial_lanes;          // lanes per instance of the broadcast kernel (0: automatic)
     arsel_schedule sched;     // ragged schedule
     uint32_t *queue;          // device counters of the persistent ragged kernel (4 x u32)
     int32_t *order;           // device work lists of the ragged kernel, grown on demand
@@ -27,6 +28,18 @@ struct arsel_ctx {
 };
 
 namespace arsel {
+
+// Broadcast selection with packed rounds (select_packed.hip): K instances of
+// one vector, uniform proposal (Q null) or integer proposal Q.
+int launch_packed(arsel_ctx *ctx, const float *alpha, const uint32_t *Q, int32_t M, int32_t K,
+                  uint64_t seed, uint64_t step, uint32_t t_max, int32_t *index, float *alpha0,
+                  uint32_t *trials, hipStream_t s);
+
+// LDS bytes the broadcast kernel needs for M reactions.
+inline size_t packed_lds_bytes(int32_t M, bool proposal)
+{
+    return (size_t)M * sizeof(float) * (proposal ? 3 : 1);
+}
 
 inline int ctx_activate(arsel_ctx *ctx)
 {

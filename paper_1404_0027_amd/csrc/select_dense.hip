@@ -470,6 +470,10 @@ extern "C" int arsel_select(arsel_ctx *ctx, const float *alpha, int32_t M, int32
     hipStream_t s = (hipStream_t)stream;
 
     const bool bcast = (layout == ARSEL_AOS && ld == 0);
+    // one vector for every instance: packed rounds (any trial width gives the
+    // same answer; the bound and debug modes keep the tile kernel)
+    if (bcast && bound == nullptr && packed_lds_bytes(M, false) + 4096 <= ctx->lds_per_block)
+        return launch_packed(ctx, alpha, nullptr, M, K, seed, step, t_max, index, alpha0, trials, s);
     const size_t row = (size_t)M * sizeof(float);
     const size_t budget = ctx->tile_lds_bytes;
     int tk = bcast ? ctx->dense_tile : (int)std::min<size_t>((size_t)ctx->dense_tile, budget / row);

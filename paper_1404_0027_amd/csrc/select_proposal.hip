@@ -168,11 +168,14 @@ extern "C" int arsel_select_proposal(arsel_ctx *ctx, const float *alpha, const u
 {
     if (!ctx) return ARSEL_ERR_NULL;
     if (M < 1 || K < 0) return ARSEL_ERR_SIZE;
-    if (lda < M || ldq < M) return ARSEL_ERR_LD;
+    if ((lda != 0 && lda < M) || (ldq != 0 && ldq < M)) return ARSEL_ERR_LD;
     if (K == 0) return ARSEL_OK;
     if (!alpha || !Q || !index) return ARSEL_ERR_NULL;
     int rc = ctx_activate(ctx);
     if (rc) return rc;
+    if (lda == 0 && ldq == 0 && packed_lds_bytes(M, true) + 4096 <= ctx->lds_per_block)
+        return launch_packed(ctx, alpha, Q, M, K, seed, step, t_max, index, nullptr, trials,
+                             (hipStream_t)stream);
     const size_t per_wave = (size_t)3 * M * sizeof(uint32_t);
     int nw = 4;
     while (nw > 1 && per_wave * nw > ctx->tile_lds_bytes) nw >>= 1;
