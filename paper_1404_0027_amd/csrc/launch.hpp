@@ -35,10 +35,14 @@ int launch_packed(arsel_ctx *ctx, const float *alpha, const uint32_t *Q, int32_t
                   uint64_t seed, uint64_t step, uint32_t t_max, int32_t *index, float *alpha0,
                   uint32_t *trials, hipStream_t s);
 
-// LDS bytes the broadcast kernel needs for M reactions.
+// LDS bytes the broadcast kernel needs for M reactions: alpha; with a
+// proposal also Q, its prefix and a guide table of 2^ceil(log2 M) entries.
 inline size_t packed_lds_bytes(int32_t M, bool proposal)
 {
-    return (size_t)M * sizeof(float) * (proposal ? 3 : 1);
+    if (!proposal) return (size_t)M * sizeof(float);
+    size_t t = 1;
+    while (t < (size_t)M) t <<= 1;
+    return ((size_t)M * 3 + t) * sizeof(uint32_t);
 }
 
 inline int ctx_activate(arsel_ctx *ctx)

@@ -55,18 +55,17 @@ __device__ __forceinline__ uint64_t block_max_u64(uint64_t x, BlockScratch<NW> &
     return m;
 }
 
-// Least j with P_j > V over the inclusive prefix P (LDS), P_{M-1} > V.
-__device__ __forceinline__ uint32_t prefix_pick(const uint32_t *P, uint32_t M, uint32_t V)
+// Least j with P_j > V over the inclusive prefix P (LDS), P_{M-1} > V, by a
+// guide table (the cutpoint method of Chen and Asau): G[b] is the least j with
+// P_j > b 2^gs, a lower bound of the answer for every V in [b 2^gs,
+// (b + 1) 2^gs), from which a forward scan reaches the answer exactly.  With
+// about one reaction per bucket the scan takes one or two steps.
+__device__ __forceinline__ uint32_t guide_pick(const uint32_t *P, const uint32_t *G, uint32_t gs,
+                                               uint32_t V)
 {
-    uint32_t lo = 0, hi = M - 1;
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (P[mid] > V)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
+    uint32_t j = G[(uint32_t)((uint64_t)V >> gs)];   // gs may be 32 (M = 1)
+    while (P[j] <= V) ++j;
+    return j;
 }
 
 struct PackedShared {
@@ -74,6 +73,7 @@ struct PackedShared {
     int32_t status;          // 0: run trials; < 0: the outcome of every instance
     uint32_t lanes_log2;
     uint32_t sumq;
+    uint32_t gs;             // guide-table bucket width log2
     float amax;
     float alpha0;
     double env;              // alpha_max (uniform) or c+ (proposal)
@@ -93,6 +93,7 @@ __global__ __launch_bounds__(NW * 64) void k_select_packed(PackedArgs a)
     float *sa = reinterpret_cast<float *>(lds_u);
     uint32_t *sq = lds_u + M;        // proposal: Q
     uint32_t *sp = lds_u + 2 * M;    // proposal: inclusive prefix of Q
+    uint32_t *sg = lds_u + 3 * M;    // proposal: guide table (2^ceil(log2 M) entries)
     const int k_lo = blockIdx.x * a.per_block;
     const int k_hi = min(a.K, k_lo + a.per_block);
 
@@ -159,9 +160,23 @@ __global__ __launch_bounds__(NW * 64) void k_select_packed(PackedArgs a)
                     run += sq[j];
                     sp[j] = (uint32_t)run;
                 }
+                // guide table: buckets of width 2^gs, at most 2^ceil(log2 M) of them
+                const int bits = 64 - __clzll((long long)SQ);
+                const uint32_t gs = (uint32_t)max(0, bits - L2);
+                __syncthreads();
+                for (uint32_t j = lo; j < hi; ++j) {
+                    const uint64_t prev = j == 0 ? 0ull : (uint64_t)sp[j - 1];
+                    const uint64_t cur = (uint64_t)sp[j];
+                    const uint64_t b0 = (prev + (1ull << gs) - 1) >> gs;
+                    const uint64_t b1 = (cur + (1ull << gs) - 1) >> gs;
+                    for (uint64_t b = b0; b < b1; ++b) sg[b] = j;
+                }
                 env = __longlong_as_double((long long)(cbits + 1));   // c+ = nextafter(c, +inf)
                 phat = a0 / (env * (double)SQ);
-                if (tid == 0) sh.sumq = (uint32_t)SQ;
+                if (tid == 0) {
+                    sh.sumq = (uint32_t)SQ;
+                    sh.gs = gs;
+                }
             }
         } else {
             phat = a0 / ((double)M * (double)amax);
@@ -205,6 +220,7 @@ __global__ __launch_bounds__(NW * 64) void k_select_packed(PackedArgs a)
     const uint64_t gmask = Lw == 64 ? ~0ull : ((1ull << Lw) - 1);
     const double envd = sh.env;
     const uint32_t SQ = prop ? sh.sumq : 0u;
+    const uint32_t gs = prop ? sh.gs : 0u;
     const uint32_t nq = prop ? SQ : M;
     const uint32_t thresh = lemire_threshold(nq);
     const uint64_t tmax = a.t_max;
@@ -246,8 +262,8 @@ __global__ __launch_bounds__(NW * 64) void k_select_packed(PackedArgs a)
             const bool oka = lemire(w.w0, nq, thresh, va) && ta < tmax;
             const bool okb = lemire(w.w2, nq, thresh, vb) && ta + 1 < tmax;
             if (prop) {
-                ja = prefix_pick(sp, M, va);
-                jb = prefix_pick(sp, M, vb);
+                ja = guide_pick(sp, sg, gs, va);
+                jb = guide_pick(sp, sg, gs, vb);
                 acca = oka && (grid_u(w.w1) * envd) * (double)sq[ja] < (double)sa[ja];
                 accb = okb && (grid_u(w.w3) * envd) * (double)sq[jb] < (double)sa[jb];
             } else {
@@ -323,8 +339,10 @@ int launch_packed(arsel_ctx *ctx, const float *alpha, const uint32_t *Q, int32_t
     a.alpha0 = Q ? nullptr : alpha0;
     a.trials = trials;
     a.lanes = ctx->trial_lanes;
-    // workgroups: about 8 per CU, at least 64 instances each
-    const int64_t slots = (int64_t)ctx->num_cu * 8;
+    // workgroups: each stages the vector once; the proposal's longer set-up
+    // (prefix, guide table, c) is amortised over more instances (about 4
+    // workgroups per CU), the uniform mode gains from more resident waves (8)
+    const int64_t slots = (int64_t)ctx->num_cu * (Q ? 4 : 8);
     int64_t per = ((int64_t)K + slots - 1) / slots;
     per = std::max<int64_t>(per, 64);
     a.per_block = (int32_t)per;
