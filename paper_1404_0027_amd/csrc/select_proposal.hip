@@ -51,30 +51,57 @@ __global__ __launch_bounds__(NW * 64) void k_select_proposal(PropArgs a)
     const float *ga = a.alpha + (int64_t)k * a.lda;
     const uint32_t *gq = a.Q + (int64_t)k * a.ldq;
 
-    // stage alpha and Q; validity, maximum, support coverage, sum Q, c
-    float amax = 0.0f;
-    bool bad = false, miss = false;
+    // stage alpha and Q with vector loads (several in flight per lane); the
+    // bit maximum of alpha certifies validity and is alpha_max (else an
+    // exact scan decides)
+    uint32_t mb = wave_max_u32(stream_bitmax<kWave>(ga, M, sa, lane));
     uint64_t sumq = 0;
-    double c = 0.0;
-    for (uint32_t j = lane; j < M; j += kWave) {
-        const float x = ga[j];
-        const uint32_t q = gq[j];
-        sa[j] = x;
+    stream_each<kWave>(reinterpret_cast<const float *>(gq), M, lane, [&](uint32_t j, float x) {
+        const uint32_t q = __float_as_uint(x);
         sq[j] = q;
-        bad |= !(x >= 0.0f) | (x == __builtin_inff());
-        amax = fmaxf(amax, x);
+        sumq += q;
+    });
+    sumq = wave_sum_u64(sumq);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float amax;
+    bool bad;
+    if (mb < 0x7F800000u) {
+        amax = __uint_as_float(mb);
+        bad = false;
+    } else {
+        wave_scan(ContigAcc{sa}, M, amax, bad);
+    }
+    // c = max over the support of fl64(alpha_j / Q_j).  Rounding is monotone,
+    // so c is fl64 of the largest exact ratio: a float estimate of each ratio
+    // (relative error < 2^-22 while the largest is above 2^-100) keeps every
+    // index within 2^-19 of the largest estimate, which contains the argmax,
+    // and only those get the binary64 division.  Tiny ratios take the exact
+    // loop over all indices.
+    bool miss = false;
+    float rmax = 0.0f;
+    for (uint32_t j = lane; j < M; j += kWave) {
+        const float x = sa[j];
         if (x > 0.0f) {
+            const uint32_t q = sq[j];
             if (q == 0)
                 miss = true;
             else
-                c = fmax(c, (double)x / (double)q);
+                rmax = fmaxf(rmax, x / (float)q);
         }
-        sumq += q;
     }
-    bad = __ballot(bad) != 0;
     miss = __ballot(miss) != 0;
-    amax = wave_max(amax);
-    sumq = wave_sum_u64(sumq);
+    rmax = wave_max(rmax);
+    const bool fast = rmax >= 0x1p-100f;
+    const float thr = rmax - rmax * 0x1p-19f;
+    double c = 0.0;
+    for (uint32_t j = lane; j < M; j += kWave) {
+        const float x = sa[j];
+        const uint32_t q = sq[j];
+        if (x > 0.0f && q != 0 && (!fast || x / (float)q >= thr))
+            c = fmax(c, (double)x / (double)q);
+    }
     c = wave_max_f64(c);
     Outcome o;
     o.trials = 0;
