@@ -58,6 +58,9 @@ def lib() -> ctypes.CDLL:
         L.orc_ssa_chain.argtypes = [P, i64, i64, i64, P, P, P, P, P, u64, u64, i64, u32, i64,
                                     P, P, i32]
         L.orc_ssa_chain.restype = i32
+        L.orc_ssa_run.argtypes = [P, i64, i64, i64, P, P, P, P, P, P, u64, u64, i64, u32, P, P,
+                                  P, i32]
+        L.orc_ssa_run.restype = i32
         _lib = L
     return _lib
 
@@ -181,3 +184,21 @@ def ssa_chain(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: 
     lib().orc_ssa_chain(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), seed, step0, steps,
                         t_max, 0 if rec_from is None else rec_from, _p(rec), _p(fired), threads)
     return x, rec, fired
+
+
+def ssa_run(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: int = 4096,
+            t0=None, ids=None, want_times: bool = False, threads: int = 1):
+    """Full SSA run (direct method with the AR selection and the time step).
+    Returns (X_final, t_final float64 [R], fired [steps, R], times or None)."""
+    x = np.array(X0, dtype=np.int32, copy=True, order="C")
+    R, N = x.shape
+    M = int(net.r0.shape[0])
+    t = np.zeros(R, np.float64) if t0 is None else np.array(t0, np.float64, copy=True)
+    fired = np.empty((steps, R), dtype=np.int32)
+    times = np.empty((steps, R), dtype=np.float64) if want_times else None
+    idv = None if ids is None else np.ascontiguousarray(ids, np.uint32)
+    arrs = [np.ascontiguousarray(v, np.int32) for v in (net.r0, net.r1, net.p0, net.p1)]
+    rate = np.ascontiguousarray(net.rate, np.float32)
+    lib().orc_ssa_run(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), _p(idv), seed, step0,
+                      steps, t_max, _p(t), _p(times), _p(fired), threads)
+    return x, t, fired, times

@@ -26,7 +26,8 @@
  *    published definition.  The paper itself only names the GPU generators
  *    it used (section "Materials").
  *  - Section "The Stochastic Simulation Algorithm" again for the SSA state
- *    update X <- X + v_j used by the jump-chain data generator.
+ *    update X <- X + v_j used by the jump-chain data generator, and for the
+ *    direct method's time step tau = ln(1/u) / alpha_0 of the full SSA run.
  *
  * Readings where the paper is silent are listed in the design notes; the
  * ones that fix arithmetic here: one Philox block b yields two trials,
@@ -451,6 +452,68 @@ int orc_ssa_chain(int32_t *X, int64_t R, int64_t N, int64_t M,
                 if (r1[j] >= 0) x[r1[j]] -= 1;
                 x[p0[j]] += 1;
                 if (p1[j] >= 0) x[p1[j]] += 1;
+            }
+        }
+        free(a);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Full SSA run (direct method, section "The Stochastic Simulation      */
+/* Algorithm"): each step recomputes every propensity from the state,   */
+/* selects the next reaction with the same uniform AR as the jump chain */
+/* (tag 2, instance id, step step0 + i), advances the time by           */
+/* tau = ln(1/u) / alpha_0 and applies the stoichiometry.  u comes from */
+/* Philox block 0xFFFFFFFE of the same stream, word 0, as               */
+/* (w + 1/2) 2^-32 in (0, 1); alpha_0 is the binary64 sum of the        */
+/* propensities in index order.  When every propensity is zero the      */
+/* state and time stay and the step records -1.                         */
+/* ids[r] (or r when ids is NULL) is realization r's instance id.       */
+/* t[r] is read and advanced in place; times (nullable) receives t after */
+/* each step at [i * R + r]; fired (nullable) the selection at [i*R+r]. */
+/* ------------------------------------------------------------------ */
+#define TAU_BLOCK 0xFFFFFFFEu
+
+int orc_ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M,
+                const int32_t *r0, const int32_t *r1, const int32_t *p0, const int32_t *p1,
+                const float *rate, const uint32_t *ids, uint64_t seed, uint64_t step0,
+                int64_t steps, uint32_t t_max, double *t, double *times, int32_t *fired,
+                int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel if (threads != 1)
+#endif
+    {
+        float *a = (float *)malloc(sizeof(float) * (size_t)M);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t r = 0; r < R; ++r) {
+            int32_t *x = X + r * N;
+            const uint32_t id = ids ? ids[r] : (uint32_t)r;
+            for (int64_t i = 0; i < steps; ++i) {
+                const uint64_t s = step0 + (uint64_t)i;
+                double a0 = 0.0;
+                for (int64_t j = 0; j < M; ++j) {
+                    a[j] = mass_action(x, r0[j], r1[j], rate[j]);
+                    a0 += (double)a[j];
+                }
+                int32_t j = select_uniform_one(a, 1, M, NULL, 0u, id, seed, s, 2u, t_max,
+                                               NULL, NULL);
+                if (fired) fired[i * R + r] = j;
+                if (j >= 0) {
+                    uint32_t w[4];
+                    draw(seed, TAU_BLOCK, id, s, 2u, w);
+                    const double u = ((double)w[0] + 0.5) * 0x1p-32;
+                    t[r] += log(1.0 / u) / a0;
+                    x[r0[j]] -= 1;
+                    if (r1[j] >= 0) x[r1[j]] -= 1;
+                    x[p0[j]] += 1;
+                    if (p1[j] >= 0) x[p1[j]] += 1;
+                }
+                if (times) times[i * R + r] = t[r];
             }
         }
         free(a);

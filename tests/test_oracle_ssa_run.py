@@ -1,0 +1,60 @@
+"""Pins of the oracle's full SSA run (direct method: AR selection, time step
+tau = ln(1/u) / alpha_0, state update; section "The Stochastic Simulation
+Algorithm"): the state sequence is the jump chain's, the times follow the
+closed-form laws of the direct method, absorbed realizations stop."""
+import numpy as np
+from scipy import stats
+
+import oracle
+from paper_1404_0027_amd import workloads
+
+
+def _decay_net(k=0.5):
+    # one reaction A -> B: alpha = k x_A, so the n firings from x_A = n take
+    # independent Exp(k i) times, i = n .. 1
+    return workloads.Network(N=2, r0=np.array([0], np.int32), r1=np.array([-1], np.int32),
+                             p0=np.array([1], np.int32), p1=np.array([-1], np.int32),
+                             rate=np.array([k], np.float32))
+
+
+def test_states_match_the_jump_chain():
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    X0 = workloads.poisson_counts(N=64, R=12, seed=5)
+    x, t, fired, _ = oracle.ssa_run(net, X0, seed=3, step0=7, steps=120, threads=4)
+    xc, _, fc = oracle.ssa_chain(net, X0, seed=3, step0=7, steps=120, threads=4)
+    assert np.array_equal(fired, fc) and np.array_equal(x, xc)
+    assert np.all(t > 0)
+
+
+def test_absorption_time_of_pure_decay():
+    n, k, R = 6, 0.5, 20000
+    net = _decay_net(k)
+    X0 = np.tile(np.array([[n, 0]], np.int32), (R, 1))
+    x, t, fired, times = oracle.ssa_run(net, X0, seed=11, step0=0, steps=n + 3,
+                                        want_times=True, threads=8)
+    assert np.all(x == np.array([0, n]))
+    assert np.all(fired[:n] == 0) and np.all(fired[n:] == -1)
+    assert np.array_equal(times[n - 1], times[-1])          # absorbed: time stays
+    i = np.arange(1, n + 1)
+    mean, var = np.sum(1.0 / (k * i)), np.sum(1.0 / (k * i) ** 2)
+    assert abs(t.mean() - mean) < 5.0 * np.sqrt(var / R)
+    assert abs(t.var() - var) < 0.1 * var
+
+
+def test_first_step_time_is_exponential():
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    R = 20000
+    X0 = np.tile(workloads.poisson_counts(N=64, R=1, seed=5), (R, 1))
+    a0 = oracle.propensities(net, X0[:1]).astype(np.float64).sum()
+    _, t, _, _ = oracle.ssa_run(net, X0, seed=2, step0=0, steps=1, threads=8)
+    assert stats.kstest(t * a0, "expon").pvalue > 0.01
+
+
+def test_instance_ids_select_the_stream():
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    X0 = workloads.poisson_counts(N=64, R=10, seed=5)
+    x, t, f, _ = oracle.ssa_run(net, X0, seed=3, step0=0, steps=40, threads=2)
+    ids = np.array([7, 2], np.uint32)
+    x2, t2, f2, _ = oracle.ssa_run(net, X0[ids], seed=3, step0=0, steps=40, ids=ids)
+    assert np.array_equal(x2, x[ids]) and np.array_equal(t2, t[ids])
+    assert np.array_equal(f2, f[:, ids])
