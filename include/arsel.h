@@ -200,6 +200,33 @@ int arsel_ssa_chain(arsel_ctx *ctx, const arsel_network *net, int32_t *X, int32_
                     uint64_t seed, uint64_t step0, int64_t steps, uint32_t t_max,
                     int64_t rec_from, int32_t *rec_X, int32_t *fired, void *stream);
 
+/* Dependency graph of the full SSA run: deps (DEVICE, [M][ARSEL_SSA_DEP_MAX]
+ * int32) lists, for each reaction j, the reactions with a reactant among the
+ * species j consumes or produces (the propensities that can change when j
+ * fires); ndeps[j] (DEVICE [M]) is their number, or -1 when there are more
+ * than ARSEL_SSA_DEP_MAX (then every propensity is recomputed after j). */
+#define ARSEL_SSA_DEP_MAX 64
+int arsel_ssa_deps(arsel_ctx *ctx, const arsel_network *net, int32_t *deps, int32_t *ndeps,
+                   void *stream);
+
+/* Full SSA run, the direct method of section "The Stochastic Simulation
+ * Algorithm" with the AR selection: for R realizations (X int32 [R][N] in
+ * place, t double [R] in place, DEVICE) and steps i = 0 .. steps-1, each step
+ * selects j exactly as arsel_ssa_chain does (uniform AR, tag-2 stream,
+ * instance r, step step0 + i), advances t by ln(1/u) / alpha_0 with
+ * u = (w + 1/2) 2^-32 from word 0 of Philox block 0xFFFFFFFE of the same
+ * stream and alpha_0 the sum of the propensities in binary64, applies the
+ * stoichiometry and recomputes the propensities of the reactions deps lists
+ * for j.  A step where nothing can fire records -1 and leaves state and
+ * time.  fired (nullable, [steps][R]) and times (nullable, [steps][R], t
+ * after each step) are outputs.  States and selections are bit-identical to
+ * the sequential definition; the times agree with it to rounding (the sum
+ * order of alpha_0 and the log implementation differ). */
+int arsel_ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
+                  const int32_t *ndeps, int32_t *X, int32_t R, uint64_t seed, uint64_t step0,
+                  int64_t steps, uint32_t t_max, double *t, double *times, int32_t *fired,
+                  void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned proposal (BF16 MLP on MFMA, FP32 accumulation).
  *

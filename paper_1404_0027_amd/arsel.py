@@ -102,7 +102,12 @@ _EXTRA_SIGNATURES = {
     "arsel_set_schedule": [_P, ctypes.POINTER(Schedule)],
     "arsel_set_dense_config": [_P, ctypes.c_int32, ctypes.c_int32],
     "arsel_set_trial_lanes": [_P, ctypes.c_int32],
+    "arsel_ssa_deps": [_P, ctypes.POINTER(Network), _P, _P, _P],
+    "arsel_ssa_run": [_P, ctypes.POINTER(Network), _P, _P, _P, ctypes.c_int32, ctypes.c_uint64,
+                      ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, _P, _P, _P, _P],
 }
+
+SSA_DEP_MAX = 64
 
 
 def _check(rc: int, what: str) -> None:

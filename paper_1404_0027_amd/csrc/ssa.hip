@@ -1,5 +1,5 @@
-// Mass-action propensities and the SSA jump chain (training data for the
-// learned proposal).
+// Mass-action propensities, the SSA jump chain (training data for the
+// learned proposal) and the full SSA run (direct method with the time step).
 //
 // Reaction j of the network consumes species r0[j] (and r1[j] when >= 0) and
 // produces p0[j] (and p1[j] when >= 0).  Its propensity is
@@ -101,6 +101,120 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_chain(ChainArgs c)
     for (int i = lane; i < N; i += kWave) gx[i] = x[i];
 }
 
+// Reactions whose propensity can change when reaction j fires: those with a
+// reactant among the species j consumes or produces.  deps[j][0 .. ndeps[j])
+// lists them; ndeps[j] = -1 when there are more than kDepMax (the run then
+// recomputes every propensity after j).
+constexpr int kDepMax = ARSEL_SSA_DEP_MAX;
+
+__global__ void k_ssa_deps(NetArgs n, int32_t *deps, int32_t *ndeps)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n.M) return;
+    const int s0 = n.r0[j], s1 = n.r1[j], s2 = n.p0[j], s3 = n.p1[j];
+    int cnt = 0;
+    for (int i = 0; i < n.M; ++i) {
+        const int a = n.r0[i], b = n.r1[i];
+        const bool hit = a == s0 || a == s1 || a == s2 || a == s3 ||
+                         (b >= 0 && (b == s0 || b == s1 || b == s2 || b == s3));
+        if (hit) {
+            if (cnt < kDepMax) deps[(int64_t)j * kDepMax + cnt] = i;
+            ++cnt;
+        }
+    }
+    ndeps[j] = cnt <= kDepMax ? cnt : -1;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        x += __longlong_as_double((long long)shfl_xor_u64((uint64_t)__double_as_longlong(x), off));
+    return x;
+}
+
+constexpr uint32_t kTauBlock = 0xFFFFFFFEu;
+
+struct RunArgs {
+    NetArgs net;
+    const int32_t *deps, *ndeps;
+    int32_t *X;          // [R][N], updated in place
+    int32_t R;
+    uint64_t seed, step0;
+    int64_t steps;
+    uint32_t t_max;
+    double *t;           // [R], advanced in place
+    double *times;       // [steps][R] or null
+    int32_t *fired;      // [steps][R] or null
+};
+
+// One wavefront per realization, counts and propensities in its LDS.  Each
+// step: exact alpha_max (bit maximum) and alpha_0 over the propensities, the
+// AR selection on the tag-2 stream (the jump chain's), tau = ln(1/u) /
+// alpha_0 with u from Philox block 0xFFFFFFFE of that stream, the
+// stoichiometry, and the propensities of the reactions the fired one
+// affects.  A step with nothing able to fire leaves state and time.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
+{
+    extern __shared__ int32_t lds_i[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int r = blockIdx.x * NW + wave;
+    if (r >= c.R) return;
+    const int N = c.net.N, M = c.net.M;
+    int32_t *x = lds_i + (size_t)wave * (N + M);
+    float *a = reinterpret_cast<float *>(x + N);
+    int32_t *gx = c.X + (int64_t)r * N;
+    for (int i = lane; i < N; i += kWave) x[i] = gx[i];
+    wave_sync_lds();
+    for (int j = lane; j < M; j += kWave) a[j] = mass_action(x, c.net.r0[j], c.net.r1[j], c.net.rate[j]);
+    wave_sync_lds();
+    double t = c.t[r];
+    for (int64_t i = 0; i < c.steps; ++i) {
+        const uint64_t s = c.step0 + (uint64_t)i;
+        uint32_t mb = 0;
+        double a0 = 0.0;
+        for (int j = lane; j < M; j += kWave) {
+            const float v = a[j];
+            mb = max(mb, __float_as_uint(v));
+            a0 += (double)v;
+        }
+        mb = wave_max_u32(mb);
+        a0 = wave_sum_f64(a0);
+        const Stream st = make_stream(c.seed, s, (uint32_t)r, kTagSSA);
+        const Outcome o = wave_select_hint(ContigAcc{a}, (uint32_t)M, mb, st, c.t_max, false);
+        const int32_t j = (int32_t)uniform_u32((uint32_t)o.index);
+        if (c.fired && lane == 0) c.fired[i * c.R + r] = j;
+        if (j >= 0) {
+            const Words w = st.block(kTauBlock);
+            const double u = ((double)w.w0 + 0.5) * 0x1p-32;
+            t += log(1.0 / u) / a0;
+            if (lane == 0) {
+                x[c.net.r0[j]] -= 1;
+                if (c.net.r1[j] >= 0) x[c.net.r1[j]] -= 1;
+                x[c.net.p0[j]] += 1;
+                if (c.net.p1[j] >= 0) x[c.net.p1[j]] += 1;
+            }
+            wave_sync_lds();
+            const int nd = (int)uniform_u32((uint32_t)c.ndeps[j]);
+            if (nd < 0) {
+                for (int jj = lane; jj < M; jj += kWave)
+                    a[jj] = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+            } else {
+                for (int l = lane; l < nd; l += kWave) {
+                    const int jj = c.deps[(int64_t)j * kDepMax + l];
+                    a[jj] = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+                }
+            }
+            wave_sync_lds();
+        }
+        if (c.times && lane == 0) c.times[i * c.R + r] = t;
+    }
+    for (int i = lane; i < N; i += kWave) gx[i] = x[i];
+    if (lane == 0) c.t[r] = t;
+}
+
 static int check_net(const arsel_network *n)
 {
     if (!n || !n->r0 || !n->r1 || !n->p0 || !n->p1 || !n->rate) return ARSEL_ERR_NULL;
@@ -152,5 +266,41 @@ extern "C" int arsel_ssa_chain(arsel_ctx *ctx, const arsel_network *net, int32_t
         hipLaunchKernelGGL(k_ssa_chain<4>, dim3((R + 3) / 4), dim3(256), per_wave * 4, s, c);
     else
         hipLaunchKernelGGL(k_ssa_chain<1>, dim3(R), dim3(64), per_wave, s, c);
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
+
+extern "C" int arsel_ssa_deps(arsel_ctx *ctx, const arsel_network *net, int32_t *deps,
+                              int32_t *ndeps, void *stream)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!deps || !ndeps) return ARSEL_ERR_NULL;
+    if ((rc = ctx_activate(ctx))) return rc;
+    hipLaunchKernelGGL(k_ssa_deps, dim3((net->M + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       net_args(net), deps, ndeps);
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
+
+extern "C" int arsel_ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
+                             const int32_t *ndeps, int32_t *X, int32_t R, uint64_t seed,
+                             uint64_t step0, int64_t steps, uint32_t t_max, double *t,
+                             double *times, int32_t *fired, void *stream)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (R < 0 || steps < 0) return ARSEL_ERR_SIZE;
+    if (R == 0 || steps == 0) return ARSEL_OK;
+    if (!deps || !ndeps || !X || !t) return ARSEL_ERR_NULL;
+    if ((rc = ctx_activate(ctx))) return rc;
+    const size_t per_wave = (size_t)(net->N + net->M) * 4;
+    if (per_wave > ctx->lds_per_block) return ARSEL_ERR_SIZE;
+    RunArgs c{net_args(net), deps, ndeps, X, R, seed, step0, steps, t_max, t, times, fired};
+    hipStream_t s = (hipStream_t)stream;
+    if (per_wave * 4 <= ctx->tile_lds_bytes)
+        hipLaunchKernelGGL(k_ssa_run<4>, dim3((R + 3) / 4), dim3(256), per_wave * 4, s, c);
+    else
+        hipLaunchKernelGGL(k_ssa_run<1>, dim3(R), dim3(64), per_wave, s, c);
     return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
 }

@@ -61,6 +61,34 @@ class DeviceNetwork:
         return rec, fired
 
 
+    def deps(self):
+        """Dependency graph of the full run (built once on the device)."""
+        if getattr(self, "_deps", None) is None:
+            d = torch.empty(self.M, arsel.SSA_DEP_MAX, dtype=torch.int32, device=self.device)
+            n = torch.empty(self.M, dtype=torch.int32, device=self.device)
+            rc = lib().arsel_ssa_deps(context(self.device), ctypes.byref(self.c), _ptr(d), _ptr(n),
+                                      _stream(self.device))
+            _check(rc, "arsel_ssa_deps")
+            self._deps = (d, n)
+        return self._deps
+
+    def run(self, X: torch.Tensor, t: torch.Tensor, *, seed: int, step0: int, steps: int,
+            t_max: int = 4096, want_fired: bool = False, want_times: bool = False):
+        """Full SSA run in place on X [R, N] (int32) and t [R] (float64);
+        returns (fired [steps, R] or None, times [steps, R] or None)."""
+        R = X.shape[0]
+        arsel._need(X, torch.int32, R * self.N, "X", self.device)
+        arsel._need(t, torch.float64, R, "t", self.device)
+        d, n = self.deps()
+        fired = torch.empty(steps, R, dtype=torch.int32, device=self.device) if want_fired else None
+        times = torch.empty(steps, R, dtype=torch.float64, device=self.device) if want_times else None
+        rc = lib().arsel_ssa_run(context(self.device), ctypes.byref(self.c), _ptr(d), _ptr(n),
+                                 _ptr(X), R, seed & (2**64 - 1), step0 & (2**64 - 1), steps, t_max,
+                                 _ptr(t), _ptr(times), _ptr(fired), _stream(self.device))
+        _check(rc, "arsel_ssa_run")
+        return fired, times
+
+
 def _round_up(x: int, m: int) -> int:
     return (x + m - 1) // m * m
 
