@@ -61,6 +61,8 @@ def lib() -> ctypes.CDLL:
         L.orc_ssa_run.argtypes = [P, i64, i64, i64, P, P, P, P, P, P, u64, u64, i64, u32, P, P,
                                   P, i32]
         L.orc_ssa_run.restype = i32
+        L.orc_select_paper.argtypes = [P, i64, i64, i64, ctypes.c_double, u64, u64, P, i32]
+        L.orc_select_paper.restype = i32
         _lib = L
     return _lib
 
@@ -202,3 +204,18 @@ def ssa_run(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: in
     lib().orc_ssa_run(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), _p(idv), seed, step0,
                       steps, t_max, _p(t), _p(times), _p(fired), threads)
     return x, t, fired, times
+
+
+PAPER_REJECT = -5
+
+
+def select_paper(alpha: np.ndarray, M: int, K: int, ld: int, *, w: float = 1.0, seed: int,
+                 step: int = 0, threads: int = 1) -> np.ndarray:
+    """The paper's election/selection scheme for K instances (alpha[k*ld + j],
+    ld = 0 broadcasts).  Returns index int32 [K] (-5: election failed)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float32)
+    idx = np.empty(K, dtype=np.int32)
+    rc = lib().orc_select_paper(_p(a), M, K, ld, float(w), seed, step, _p(idx), threads)
+    if rc != 0:
+        raise ValueError("orc_select_paper rejected its arguments")
+    return idx

@@ -520,3 +520,55 @@ int orc_ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M,
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* The paper's own scheme (section "A GPU acceptance-rejection          */
+/* algorithm (GPU/AR) for SSA", election and selection steps): every    */
+/* reaction j draws u_j in [0, T), is eligible when u_j < D_j (D_j > 0)  */
+/* and is rated R_j = u_j / D_j; the eligible reaction with the lowest  */
+/* rating is selected, and when none is eligible the election fails    */
+/* (the paper returns M + 1; here -5).  T = w * alpha_max (the paper's  */
+/* T_w).  Reaction j takes word j mod 4 of Philox block j / 4 of the     */
+/* tag-3 stream (instance k, step s): u_j = w_j 2^-32 T in binary64.     */
+/* The pseudo-code's default rating 10 T for a non-eligible reaction    */
+/* can undercut real ratings when T < 0.1; here a non-eligible reaction */
+/* never wins.  Equal ratings go to the least index.  The law is not    */
+/* alpha_j / alpha_0 (see oracle/laws.py, paper_law).                   */
+/* ------------------------------------------------------------------ */
+static int32_t select_paper_one(const float *a, int64_t stride, int64_t M, double w,
+                                uint32_t k, uint64_t seed, uint64_t step)
+{
+    float amax;
+    if (scan_max(a, stride, M, &amax) != 0) return -2;
+    if (amax == 0.0f) return -1;
+    const double T = w * (double)amax;
+    int32_t best = -5;
+    double best_r = 0.0;
+    uint32_t words[4];
+    for (int64_t j = 0; j < M; ++j) {
+        if ((j & 3) == 0) draw(seed, (uint32_t)(j >> 2), k, step, 3u, words);
+        const double u = grid_u(words[j & 3]) * T;
+        const double d = (double)a[j * stride];
+        if (d > 0.0 && u < d) {
+            const double r = u / d;
+            if (best < 0 || r < best_r) {
+                best = (int32_t)j;
+                best_r = r;
+            }
+        }
+    }
+    return best;
+}
+
+int orc_select_paper(const float *alpha, int64_t M, int64_t K, int64_t ld, double w,
+                     uint64_t seed, uint64_t step, int32_t *index, int threads)
+{
+    if (M < 1 || K < 0 || (ld != 0 && ld < M) || !(w > 0.0)) return -1;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(static) if (threads != 1)
+#endif
+    for (int64_t k = 0; k < K; ++k)
+        index[k] = select_paper_one(alpha + k * ld, 1, M, w, (uint32_t)k, seed, step);
+    return 0;
+}

@@ -174,3 +174,35 @@ def chi_square_p(counts: np.ndarray, probs: np.ndarray, min_expected: float = 5.
     stat = float(((obs_b - exp_b) ** 2 / exp_b).sum())
     dof = max(len(obs_b) - 1, 1)
     return float(chi2.sf(stat, dof))
+
+
+def paper_law(alpha: np.ndarray, w: float = 1.0) -> tuple[np.ndarray, float]:
+    """Law of the paper's election/selection scheme (continuous u), and the
+    probability that the election fails.
+
+    With d_j = alpha_j / T, T = w alpha_max, the ratings R_j = T U_j / alpha_j
+    of the eligible reactions (R_j < 1) are independent and P(R_j > r) =
+    1 - d_j r on [0, 1/d_j]; the least of them is j with probability
+        P(j) = d_j * integral_0^min(1, 1/d_max) prod_{i != j} (1 - d_i r)_+ dr,
+    and no reaction is eligible with probability prod_j (1 - d_j)_+ (zero when
+    w <= 1).  The integrand is a polynomial of degree < M on the interval, so
+    Gauss-Legendre with M nodes integrates it exactly (up to rounding)."""
+    a = np.asarray(alpha, np.float64)
+    T = w * a.max()
+    d = a / T
+    hi = min(1.0, 1.0 / d.max())
+    n = max(8, a.size)
+    x, wt = np.polynomial.legendre.leggauss(n)
+    r = 0.5 * hi * (x + 1.0)
+    wt = 0.5 * hi * wt
+    terms = 1.0 - np.outer(r, d)                    # [nodes, M], > 0 inside the interval
+    logt = np.log(np.where(d > 0, terms, 1.0))
+    total = logt.sum(axis=1)
+    law = np.empty(a.size)
+    for j in range(a.size):
+        if d[j] == 0:
+            law[j] = 0.0
+            continue
+        law[j] = d[j] * np.sum(wt * np.exp(total - logt[:, j]))
+    reject = float(np.prod(np.clip(1.0 - d, 0.0, None))) if w > 1 else 0.0
+    return law, reject
