@@ -174,6 +174,22 @@ int arsel_select_proposal(arsel_ctx *ctx, const float *alpha, const uint32_t *Q,
                           int32_t K, int64_t lda, int64_t ldq, uint64_t seed, uint64_t step,
                           uint32_t t_max, int32_t *index, uint32_t *trials, void *stream);
 
+/*
+ * The paper's own scheme (section "A GPU acceptance-rejection algorithm
+ * (GPU/AR) for SSA": election and selection steps), for comparison: every
+ * reaction j draws u_j = w_j 2^-32 T with T = w * alpha_max (the paper's
+ * T_w; w > 0), w_j being word j mod 4 of Philox block j/4 of the tag-3
+ * stream (instance k, step); j is eligible when u_j < alpha_j and rated
+ * u_j / alpha_j; the eligible reaction with the lowest rating is returned
+ * (least index on ties), -5 when none is eligible (the paper's M + 1), -1
+ * when every alpha_j is 0, -2 for NaN / negative / +inf.  alpha[k*ld + j]
+ * (DEVICE), ld == 0 broadcasts one vector, else ld >= M.  The law of this
+ * scheme is NOT alpha_j / alpha_0 (it is biased towards large propensities
+ * for small M); bit-identical to the sequential definition.
+ */
+int arsel_select_paper(arsel_ctx *ctx, const float *alpha, int32_t M, int32_t K, int64_t ld,
+                       double w, uint64_t seed, uint64_t step, int32_t *index, void *stream);
+
 /* Mass-action network (DEVICE arrays of M entries): reaction j consumes
  * species r0[j] and, when r1[j] >= 0, r1[j]; it produces p0[j] and, when
  * p1[j] >= 0, p1[j].  Species indices must lie in [0, N). */

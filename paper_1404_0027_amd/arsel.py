@@ -102,6 +102,8 @@ _EXTRA_SIGNATURES = {
     "arsel_set_schedule": [_P, ctypes.POINTER(Schedule)],
     "arsel_set_dense_config": [_P, ctypes.c_int32, ctypes.c_int32],
     "arsel_set_trial_lanes": [_P, ctypes.c_int32],
+    "arsel_select_paper": [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                           ctypes.c_uint64, ctypes.c_uint64, _P, _P],
     "arsel_ssa_deps": [_P, ctypes.POINTER(Network), _P, _P, _P],
     "arsel_ssa_run": [_P, ctypes.POINTER(Network), _P, _P, _P, ctypes.c_int32, ctypes.c_uint64,
                       ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, _P, _P, _P, _P],
@@ -320,6 +322,25 @@ def select_proposal_broadcast(alpha: torch.Tensor, Q: torch.Tensor, K: int, *, s
                                      _ptr(trials), _stream(dev))
     _check(rc, "arsel_select_proposal")
     return index, trials
+
+
+PAPER_REJECT = -5
+
+
+def select_paper(alpha: torch.Tensor, M: int, K: int, ld: int, *, w: float = 1.0, seed: int,
+                 step: int = 0, index: torch.Tensor | None = None) -> torch.Tensor:
+    """The paper's election/selection scheme (arsel_select_paper): K instances
+    of alpha[k*ld + j] (ld = 0 broadcasts); -5 marks a failed election."""
+    dev = alpha.device
+    need = M if ld == 0 else (K - 1) * ld + M if K > 0 else 0
+    _need(alpha, torch.float32, need, "alpha", dev)
+    if index is None:
+        index = torch.empty(K, dtype=torch.int32, device=dev)
+    _need(index, torch.int32, K, "index", dev)
+    rc = lib().arsel_select_paper(context(dev), _ptr(alpha), M, K, ld, float(w),
+                                  seed & (2**64 - 1), step & (2**64 - 1), _ptr(index), _stream(dev))
+    _check(rc, "arsel_select_paper")
+    return index
 
 
 def gemm_bf16(A: torch.Tensor, lda: int, a_kcontig: bool, B: torch.Tensor, ldb: int,
