@@ -217,6 +217,82 @@ def bench_learned(torch, np, arsel, workloads, epochs: int = 3):
                                      "speedup": round(rl / ru, 2)}}}
 
 
+def bench_ssa(torch, np, workloads):
+    """Full batched SSA on the N=641 / M=1029 mass-action network: R = 16384
+    realizations x 10^4 steps, one launch (selection, time step,
+    stoichiometry, dependency-graph propensity updates per step)."""
+    from paper_1404_0027_amd import learned
+
+    net = workloads.mass_action_network()
+    dn = learned.DeviceNetwork(net)
+    R, steps = 16384, 10000
+    X0 = torch.from_numpy(workloads.poisson_counts(N=net.N, R=R, seed=5)).cuda()
+    X = X0.clone()
+    t = torch.zeros(R, dtype=torch.float64, device="cuda")
+    dn.run(X, t, seed=SEED, step0=0, steps=100)            # warm-up (and the dependency graph)
+    X.copy_(X0)
+    t.zero_()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    dn.run(X, t, seed=SEED, step0=0, steps=steps)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    # the jump chain kernel (full propensity recompute each step) for reference
+    X.copy_(X0)
+    torch.cuda.synchronize()
+    e0.record()
+    dn.chain(X, seed=SEED, step0=0, steps=1000)
+    e1.record()
+    torch.cuda.synchronize()
+    sec_chain = e0.elapsed_time(e1) * 1e-3 * (steps / 1000)
+    return {"workload": "full SSA, mass-action network N=641, M=1029, counts Poisson(50): "
+                        f"R={R} realizations x {steps} steps in one launch",
+            "selections_per_s": round(R * steps / sec, 1), "seconds": round(sec, 4),
+            "mean_simulated_time": float(t.mean().item()),
+            "jump_chain_full_recompute_selections_per_s": round(R * steps / sec_chain, 1),
+            "note": "per step: exact alpha_max and alpha_0 over LDS-resident propensities, AR "
+                    "selection, tau, stoichiometry, propensities of the affected reactions"}
+
+
+def bench_paper_table1(torch, np, arsel, workloads):
+    """Table-1-style quality run: 10^7 selections from each discrete Gaussian
+    (M = 64, 256, 1024; K = 62500 instances x 160 steps), the paper's
+    election/selection scheme (T = alpha_max) against exact AR; MSE between
+    the normalised propensities and the observed frequencies, and the
+    selections/s of each."""
+    K, steps = 62500, 160
+    out = {}
+    idx = torch.empty(K, dtype=torch.int32, device="cuda")
+    for M in (64, 256, 1024):
+        a_np = workloads.gaussian_vector(M)
+        a = torch.from_numpy(a_np).cuda()
+        p = a_np.astype(np.float64) / a_np.astype(np.float64).sum()
+        row = {}
+        for name, fn in (("paper_scheme", lambda s: arsel.select_paper(a, M, K, 0, w=1.0, seed=SEED,
+                                                                        step=s, index=idx)),
+                         ("exact_AR", lambda s: arsel.select(a, M, K, 0, arsel.AOS, seed=SEED, step=s,
+                                                             index=idx))):
+            counts = torch.zeros(M + 1, dtype=torch.int64, device="cuda")
+            for s in range(steps):
+                fn(s)
+                counts += torch.bincount(idx.clamp(min=-1) + 1, minlength=M + 1)[:M + 1].roll(-1)
+            c = counts.cpu().numpy()
+            freq = c[:M] / float(K * steps)
+            big = p >= 1.0 / (4 * M)          # reactions with >= 2.5e6 / M expected selections
+            row[name] = {"mse": float(np.mean((freq - p) ** 2)),
+                         "max_rel_err_large_p": float(np.max(np.abs(freq[big] - p[big]) / p[big])),
+                         "rejections": int(c[M]),
+                         "selections_per_s": round(K / _timed(torch, fn, 20), 1)}
+        out[str(M)] = row
+    return {"workload": f"discrete Gaussian propensities (section on test and validation), "
+                        f"{K} instances x {steps} steps = 10^7 selections per M, T = alpha_max",
+            "by_M": out,
+            "note": "MSE = mean_j (alpha_j / alpha_0 - observed frequency_j)^2; exact AR sits at "
+                    "the multinomial sampling floor, the paper's scheme adds its bias"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,12 +386,16 @@ def main() -> int:
         cpu, parity = cpu_baseline(host, threads=min(16, os.cpu_count() or 1), last_step=last,
                                    gpu_index=got)
 
-    ragged = learned_res = None
+    ragged = learned_res = ssa_res = paper_res = None
     if not args.no_extras:
         print("[bench] uneven batch", file=sys.stderr, flush=True)
         ragged = bench_ragged(torch, arsel, workloads)
         print("[bench] learned proposal", file=sys.stderr, flush=True)
         learned_res = bench_learned(torch, np, arsel, workloads)
+        print("[bench] full SSA run", file=sys.stderr, flush=True)
+        ssa_res = bench_ssa(torch, np, workloads)
+        print("[bench] paper scheme vs exact AR (Table 1 style)", file=sys.stderr, flush=True)
+        paper_res = bench_paper_table1(torch, np, arsel, workloads)
         acceptance["learned_per_trial"] = learned_res["per_state"]["acceptance_per_trial"]["learned"]
         acceptance["uniform_per_trial_same_states"] = (
             learned_res["per_state"]["acceptance_per_trial"]["uniform"])
@@ -336,6 +416,8 @@ def main() -> int:
         "parity_last_step": parity,
         "ragged": ragged,
         "learned": learned_res,
+        "ssa_run": ssa_res,
+        "paper_table1": paper_res,
     }
     print(json.dumps(out), flush=True)
     return 1 if parity.startswith("MISMATCH") else 0
