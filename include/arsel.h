@@ -105,7 +105,9 @@ int arsel_select(arsel_ctx *ctx, const float *alpha, int32_t M, int32_t K, int64
                  uint32_t *trials, void *stream);
 
 /* Dense-path schedule: at most `tile` instances per workgroup tile (1..64)
- * and `waves` wavefronts per workgroup (4, 8 or 16).  Results never change. */
+ * and `waves` wavefronts per workgroup (4, 8 or 16); tile = waves = 0
+ * restores the default (16-instance tiles, 16 wavefronts when the launch has
+ * at most one tile per compute unit, else 8).  Results never change. */
 int arsel_set_dense_config(arsel_ctx *ctx, int32_t tile, int32_t waves);
 
 /*

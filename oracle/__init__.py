@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
         L.orc_ssa_run.restype = i32
         L.orc_select_paper.argtypes = [P, i64, i64, i64, ctypes.c_double, u64, u64, P, i32]
         L.orc_select_paper.restype = i32
+        L.orc_select_ids.argtypes = [P, i64, i64, P, u64, u64, u32, P, P, P, i32]
+        L.orc_select_ids.restype = i32
         _lib = L
     return _lib
 
@@ -219,3 +221,20 @@ def select_paper(alpha: np.ndarray, M: int, K: int, ld: int, *, w: float = 1.0, 
     if rc != 0:
         raise ValueError("orc_select_paper rejected its arguments")
     return idx
+
+
+def select_ids(rows: np.ndarray, ids, *, seed: int, step: int = 0, t_max: int = 4096,
+               threads: int = 1):
+    """Uniform AR on rows [n, M] that are instances ids[i] of a larger batch.
+    Returns (index, alpha0, trials)."""
+    a = np.ascontiguousarray(rows, dtype=np.float32)
+    n, M = a.shape
+    idv = np.ascontiguousarray(ids, np.uint32)
+    idx = np.empty(n, np.int32)
+    a0 = np.empty(n, np.float32)
+    tr = np.empty(n, np.uint32)
+    rc = lib().orc_select_ids(_p(a), M, n, _p(idv), seed, step, t_max, _p(idx), _p(a0), _p(tr),
+                              threads)
+    if rc != 0:
+        raise ValueError("orc_select_ids rejected its arguments")
+    return idx, a0, tr

@@ -572,3 +572,21 @@ int orc_select_paper(const float *alpha, int64_t M, int64_t K, int64_t ld, doubl
         index[k] = select_paper_one(alpha + k * ld, 1, M, w, (uint32_t)k, seed, step);
     return 0;
 }
+
+/* Uniform AR for n instances given as rows alpha[i*M + j] whose instance ids
+ * (Philox stream) are ids[i]: the same selection as orc_select_uniform gives
+ * instance ids[i] of a larger batch, for checking sampled instances. */
+int orc_select_ids(const float *alpha, int64_t M, int64_t n, const uint32_t *ids,
+                   uint64_t seed, uint64_t step, uint32_t t_max, int32_t *index,
+                   float *alpha0, uint32_t *trials, int threads)
+{
+    if (M < 1 || n < 0 || !ids) return -1;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 1) if (threads != 1)
+#endif
+    for (int64_t i = 0; i < n; ++i)
+        index[i] = select_uniform_one(alpha + i * M, 1, M, NULL, 0u, ids[i], seed, step, 0u,
+                                      t_max, alpha0 ? alpha0 + i : NULL, trials ? trials + i : NULL);
+    return 0;
+}

@@ -200,7 +200,8 @@ def select_raw(ctx, alpha_ptr: int, M: int, K: int, ld: int, layout: int, bound_
 
 
 def set_dense_config(tile: int, waves: int, device=None) -> None:
-    """Instances per dense tile and wavefronts per workgroup (results unchanged)."""
+    """Instances per dense tile and wavefronts per workgroup (results
+    unchanged); (0, 0) restores the automatic choice."""
     _check(lib().arsel_set_dense_config(context(device), tile, waves), "arsel_set_dense_config")
 
 

@@ -26,7 +26,7 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     // Two dense tiles per compute unit (160 KB of LDS on gfx950).
     c->tile_lds_bytes = std::min<size_t>(c->lds_per_block, 80 * 1024);
     c->dense_tile = 16;
-    c->dense_waves = 16;
+    c->dense_waves = 0;        // automatic (see launch_tile)
     c->trial_lanes = 0;
     c->sched.wave_max_m = 1024;
     c->sched.block_waves = 8;
@@ -108,6 +108,11 @@ extern "C" int arsel_set_schedule(arsel_ctx *ctx, const arsel_schedule *s)
 extern "C" int arsel_set_dense_config(arsel_ctx *ctx, int32_t tile, int32_t waves)
 {
     if (!ctx) return ARSEL_ERR_NULL;
+    if (tile == 0 && waves == 0) {          // back to the automatic choice
+        ctx->dense_tile = 16;
+        ctx->dense_waves = 0;
+        return ARSEL_OK;
+    }
     if (tile < 1 || tile > 64) return ARSEL_ERR_ARG;
     if (!(waves == 4 || waves == 8 || waves == 16)) return ARSEL_ERR_ARG;
     ctx->dense_tile = tile;

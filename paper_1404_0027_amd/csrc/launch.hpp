@@ -14,7 +14,7 @@ struct arsel_ctx {
     size_t lds_per_block;     // device limit on LDS per workgroup (bytes)
     size_t tile_lds_bytes;    // LDS budget of one dense tile
     int dense_tile;           // instances per dense tile (upper bound)
-    int dense_waves;          // wavefronts per dense workgroup (4, 8, 16)
+    int dense_waves;          // wavefronts per dense workgroup (4, 8, 16; 0: automatic)
     int trial_lanes;          // lanes per instance of the broadcast kernel (0: automatic)
     arsel_schedule sched;     // ragged schedule
     uint32_t *queue;          // device counters of the persistent ragged kernel (4 x u32)

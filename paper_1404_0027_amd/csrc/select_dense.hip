@@ -418,7 +418,14 @@ __global__ __launch_bounds__(NW * 64) void k_select_global(DenseArgs a)
 
 int launch_tile(arsel_ctx *ctx, const DenseArgs &a, int grid, size_t lds, hipStream_t s)
 {
-    switch (ctx->dense_waves) {
+    // Automatic choice (no explicit configuration): a launch of about one
+    // tile per CU finishes sooner with 16 wavefronts sharing each tile's
+    // rounds; with several tiles per CU, 8 wavefronts per tile let two tiles
+    // overlap on a CU (measured: 1.54 vs 1.26 TB/s at 256 tiles, 2.73 vs 2.32
+    // at 4096 tiles, 3.12 vs 2.51 at 62500 tiles).
+    int waves = ctx->dense_waves;
+    if (waves == 0) waves = grid <= ctx->num_cu ? 16 : 8;
+    switch (waves) {
     case 4:
         hipLaunchKernelGGL(k_select_tile<4>, dim3(grid), dim3(256), lds, s, a);
         break;

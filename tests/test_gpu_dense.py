@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_1404_0027_amd import arsel, workloads
 from tests.parity import assert_same, dense_both
 
@@ -127,7 +128,7 @@ def test_dense_schedule_does_not_change_results(gpu, tile, waves):
         g, o = dense_both(a, 1029, 1024, 1029, AOS, seed=1, step=4)
         assert_same(g, o, f"aos tile {tile} waves {waves}")
     finally:
-        arsel.set_dense_config(16, 16)
+        arsel.set_dense_config(0, 0)
 
 
 def test_host_argument_errors(gpu):
@@ -155,3 +156,21 @@ def test_repeatable(gpu):
     r2 = arsel.select(t, 1029, 4096, 4096, SOA, seed=7, step=3)[0].cpu()
     r3 = arsel.select(t, 1029, 4096, 4096, SOA, seed=7, step=4)[0].cpu()
     assert torch.equal(r1, r2) and not torch.equal(r1, r3)
+
+
+def test_million_realizations_sampled(gpu):
+    """10^6 realizations x M = 1029 (SoA, 4.1 GB) in one launch; 96 sampled
+    instances (and the last ones, in the ragged last tile) checked against
+    the oracle by instance id."""
+    M, K = 1029, 1_000_000
+    g = torch.Generator(device="cuda").manual_seed(123)
+    a = torch.empty(M, K, device="cuda").log_normal_(0.0, 2.0, generator=g)
+    a[torch.rand(M, K, device="cuda", generator=g) < 0.3] = 0.0
+    idx, a0, tr = arsel.select(a, M, K, K, arsel.SOA, seed=5, step=2, want_alpha0=True,
+                               want_trials=True)
+    ids = np.unique(np.r_[np.random.default_rng(0).choice(K, 96, replace=False), K - 3, K - 2, K - 1])
+    rows = a[:, torch.from_numpy(ids.astype(np.int64)).cuda()].T.contiguous().cpu().numpy()
+    oi, oa, ot = oracle.select_ids(rows, ids.astype(np.uint32), seed=5, step=2, threads=8)
+    assert np.array_equal(idx.cpu().numpy()[ids], oi)
+    assert np.array_equal(tr.cpu().numpy().view(np.uint32)[ids], ot)
+    assert np.array_equal(a0.cpu().numpy()[ids].view(np.uint32), oa.view(np.uint32))

@@ -285,3 +285,13 @@ def test_threads_do_not_change_results():
     r8 = oracle.select_uniform(a, 1029, 512, 512, oracle.SOA, seed=1, step=4, threads=8)
     for x, y in zip(r1, r8):
         assert np.array_equal(x, y)
+
+
+def test_select_ids_matches_the_batch():
+    """Rows checked by instance id give the batch's answers for those ids."""
+    a = workloads.lognormal_soa(M=300, K=200, seed=2)[0]
+    i, a0, t = oracle.select_uniform(a, 300, 200, 200, oracle.SOA, seed=4, step=3)
+    ids = np.array([0, 17, 199, 5], np.uint32)
+    i2, a02, t2 = oracle.select_ids(a[:, ids].T, ids, seed=4, step=3)
+    assert np.array_equal(i[ids], i2) and np.array_equal(t[ids], t2)
+    assert np.array_equal(a0[ids].view(np.uint32), a02.view(np.uint32))
