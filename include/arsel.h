@@ -169,8 +169,9 @@ int arsel_set_schedule(arsel_ctx *ctx, const arsel_schedule *s);
  * Q_j = 0 for some alpha_j > 0, or sum Q >= 2^32 (after the -2 / -1 checks).
  * lda == 0 (ldq == 0) gives every instance the same alpha (Q); otherwise
  * lda, ldq >= M (ARSEL_ERR_LD).  With both 0 the broadcast kernel with packed
- * rounds runs (see arsel_set_trial_lanes).  M up to ~13000 (alpha, Q and the
- * prefix of one instance live in LDS); ARSEL_ERR_SIZE beyond.
+ * rounds runs (see arsel_set_trial_lanes).  alpha and the prefix of Q of an
+ * instance live in LDS: M up to ~20000 (~10000 in the broadcast kernel, which
+ * also keeps Q and a guide table); ARSEL_ERR_SIZE beyond.
  */
 int arsel_select_proposal(arsel_ctx *ctx, const float *alpha, const uint32_t *Q, int32_t M,
                           int32_t K, int64_t lda, int64_t ldq, uint64_t seed, uint64_t step,

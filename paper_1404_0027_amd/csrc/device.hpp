@@ -139,6 +139,20 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x)
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
+// Inclusive prefix sum over the 64 lanes (u32, wrapping) with DPP: row
+// shifts 1, 2, 4, 8 scan each row of 16 lanes, then row broadcasts carry the
+// totals of rows 0..2 into the rows above.  No LDS traffic.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x)
+{
+    x += dpp_u32<0x111>(x);          // row_shr:1
+    x += dpp_u32<0x112>(x);          // row_shr:2
+    x += dpp_u32<0x114>(x);          // row_shr:4
+    x += dpp_u32<0x118>(x);          // row_shr:8
+    x += dpp_u32<0x142, 0xA>(x);     // row_bcast:15 into rows 1 and 3
+    x += dpp_u32<0x143, 0xC>(x);     // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
 // Maximum over the lanes of the same row whose index is congruent mod 4:
 // lane l returns max over lanes (l & ~15) + ((l + 4 i) & 15), i = 0..3.
 __device__ __forceinline__ uint32_t row_max_mod4(uint32_t x)

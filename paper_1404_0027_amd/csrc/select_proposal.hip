@@ -45,9 +45,11 @@ __global__ __launch_bounds__(NW * 64) void k_select_proposal(PropArgs a)
     const int k = blockIdx.x * NW + wave;
     if (k >= a.K) return;
     const uint32_t M = (uint32_t)a.M;
-    float *sa = reinterpret_cast<float *>(lds_u) + (size_t)wave * 3 * M;
-    uint32_t *sq = lds_u + (size_t)wave * 3 * M + M;
-    uint32_t *sp = sq + M;
+    // per wave: alpha, then Q (replaced in place by its inclusive prefix P
+    // once c is known; Q_j = P_j - P_{j-1} afterwards)
+    float *sa = reinterpret_cast<float *>(lds_u) + (size_t)wave * 2 * M;
+    uint32_t *sq = lds_u + (size_t)wave * 2 * M + M;
+    uint32_t *sp = sq;
     const float *ga = a.alpha + (int64_t)k * a.lda;
     const uint32_t *gq = a.Q + (int64_t)k * a.ldq;
 
@@ -112,18 +114,18 @@ __global__ __launch_bounds__(NW * 64) void k_select_proposal(PropArgs a)
     else if (miss || sumq >= (1ull << 32))
         o.index = -4;
     else {
-        // inclusive prefix of Q (exact: sum Q < 2^32)
-        uint32_t carry = 0;
-        for (uint32_t base = 0; base < M; base += kWave) {
-            const uint32_t j = base + lane;
-            uint32_t v = j < M ? sq[j] : 0u;
-#pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const uint32_t y = (uint32_t)__shfl_up((int)v, d, kWave);
-                if (lane >= d) v += y;
+        // inclusive prefix of Q (exact: sum Q < 2^32): lane l owns the
+        // contiguous range [l per, (l + 1) per), one DPP scan of the range sums
+        {
+            const uint32_t per = (M + kWave - 1) / kWave;
+            const uint32_t lo = min((uint32_t)lane * per, M), hi = min(lo + per, M);
+            uint32_t part = 0;
+            for (uint32_t j = lo; j < hi; ++j) part += sq[j];
+            uint32_t run = wave_incl_scan_u32(part) - part;
+            for (uint32_t j = lo; j < hi; ++j) {
+                run += sq[j];
+                sp[j] = run;          // in place: sp aliases sq
             }
-            if (j < M) sp[j] = carry + v;
-            carry += readlane_u32(v, kWave - 1);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -146,7 +148,8 @@ __global__ __launch_bounds__(NW * 64) void k_select_proposal(PropArgs a)
         };
         auto accept = [&](uint32_t j, uint32_t uw) {
             const double uc = grid_u(uw) * cplus;
-            return uc * (double)sq[j] < (double)sa[j];
+            const uint32_t qj = sp[j] - (j ? sp[j - 1] : 0u);
+            return uc * (double)qj < (double)sa[j];
         };
         uint64_t key = kNoAccept;
         for (uint32_t r = 0; r < rounds && key == kNoAccept; r = uniform_u32(r + 1)) {
@@ -203,7 +206,7 @@ extern "C" int arsel_select_proposal(arsel_ctx *ctx, const float *alpha, const u
     if (lda == 0 && ldq == 0 && packed_lds_bytes(M, true) + 4096 <= ctx->lds_per_block)
         return launch_packed(ctx, alpha, Q, M, K, seed, step, t_max, index, nullptr, trials,
                              (hipStream_t)stream);
-    const size_t per_wave = (size_t)3 * M * sizeof(uint32_t);
+    const size_t per_wave = (size_t)2 * M * sizeof(uint32_t);
     int nw = 4;
     while (nw > 1 && per_wave * nw > ctx->tile_lds_bytes) nw >>= 1;
     if (per_wave * nw > ctx->lds_per_block) return ARSEL_ERR_SIZE;
