@@ -25,14 +25,22 @@ typedef float f32x4m __attribute__((ext_vector_type(4)));
 // GEMM: C[m][n] = sum_k A(m, k) B(n, k), BF16 inputs, FP32 accumulation on
 // v_mfma_f32_16x16x32_bf16.  A(m,k) = A[m*lda + k] when A_KC (k contiguous)
 // else A[k*lda + m]; B(n,k) = B[n*ldb + k] when B_KC else B[k*ldb + n].
-// Workgroup tile 64 x 64, 4 wavefronts of 32 x 32 (2 x 2 MFMA blocks), K step 32.
-// Epilogue: + bias[n], ReLU, zero where mask(m, n) <= 0, FP32 and/or BF16 out.
+// Workgroup tile 64 x 64, 4 wavefronts of 32 x 32 (2 x 2 MFMA blocks), K step
+// 32.  Each thread moves one 16-byte chunk (8 BF16) of each operand tile per
+// step; the next step's chunks are loaded into registers while the MFMAs of
+// the current step run.  With grid.z > 1 the K range is split into grid.z
+// slices of kslice (a multiple of 32) and slice z writes its partial product
+// to C + z * M * ldc (summed afterwards in slice order); the epilogue then
+// runs in the reduction.  Epilogue: + bias[n], ReLU, zero where
+// mask(m, n) <= 0, FP32 and/or BF16 out.
 // ---------------------------------------------------------------------------
 struct GemmArgs {
     const __bf16 *A;
     const __bf16 *B;
     int64_t lda, ldb;
     int32_t M, N, K;
+    int32_t kslice;           // K range per grid.z slice (multiple of 32)
+    int32_t vec_a, vec_b;     // 16-byte chunks allowed (aligned base, ld % 8 == 0)
     const float *bias;        // [N] or null
     const __bf16 *mask;       // [M][ldm] or null
     int64_t ldm;
@@ -47,56 +55,102 @@ constexpr int kGT = 64;      // tile edge
 constexpr int kGK = 32;      // k step
 constexpr int kGPad = 8;     // LDS row padding (bf16)
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One thread's 8-element chunk of a 64 x 32 operand tile.  KC: row t/4,
+// k offset 8 (t % 4); otherwise k row t/8, 8 consecutive m at 8 (t % 8).
 template <bool KC>
-__device__ __forceinline__ void gemm_load_tile(const __bf16 *X, int64_t ld, int rows, int K, int r0,
-                                               int k0, __bf16 (*S)[kGK + kGPad])
-{
-    const int t = threadIdx.x;   // 256 threads, 64 x 32 elements, 8 per thread
-    if (KC) {
-        const int r = t >> 2, kk = (t & 3) * 8;
-        const int gr = r0 + r, gk = k0 + kk;
+struct Chunk {
+    u32x4 v;
+
+    __device__ __forceinline__ void load(const __bf16 *X, int64_t ld, int rows, int K, int r0,
+                                         int k0, bool vec)
+    {
+        const int t = threadIdx.x;
+        union {
+            u32x4 u;
+            __bf16 h[8];
+        } c;
+        if (KC) {
+            const int r = t >> 2, kk = (t & 3) * 8;
+            const int gr = r0 + r, gk = k0 + kk;
+            const __bf16 *p = X + (int64_t)gr * ld + gk;
+            if (vec && gr < rows && gk + 8 <= K) {
+                c.u = *reinterpret_cast<const u32x4 *>(p);
+            } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-            S[r][kk + e] = (gr < rows && gk + e < K) ? X[(int64_t)gr * ld + gk + e] : (__bf16)0.0f;
-    } else {
-        const int kk = t >> 3, rr = (t & 7) * 8;
-        const int gk = k0 + kk;
+                for (int e = 0; e < 8; ++e) c.h[e] = (gr < rows && gk + e < K) ? p[e] : (__bf16)0.0f;
+            }
+        } else {
+            const int kk = t >> 3, rr = (t & 7) * 8;
+            const int gk = k0 + kk, gr = r0 + rr;
+            const __bf16 *p = X + (int64_t)gk * ld + gr;
+            if (vec && gk < K && gr + 8 <= rows) {
+                c.u = *reinterpret_cast<const u32x4 *>(p);
+            } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int gr = r0 + rr + e;
-            S[rr + e][kk] = (gr < rows && gk < K) ? X[(int64_t)gk * ld + gr] : (__bf16)0.0f;
+                for (int e = 0; e < 8; ++e) c.h[e] = (gk < K && gr + e < rows) ? p[e] : (__bf16)0.0f;
+            }
+        }
+        v = c.u;
+    }
+
+    __device__ __forceinline__ void store(__bf16 (*S)[kGK + kGPad]) const
+    {
+        const int t = threadIdx.x;
+        if (KC) {
+            *reinterpret_cast<u32x4 *>(&S[t >> 2][(t & 3) * 8]) = v;
+        } else {
+            union {
+                u32x4 u;
+                __bf16 h[8];
+            } c;
+            c.u = v;
+            const int kk = t >> 3, rr = (t & 7) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) S[rr + e][kk] = c.h[e];
         }
     }
-}
+};
 
 template <bool A_KC, bool B_KC>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
-    __shared__ __bf16 sA[kGT][kGK + kGPad];
-    __shared__ __bf16 sB[kGT][kGK + kGPad];
+    __shared__ __attribute__((aligned(16))) __bf16 sA[kGT][kGK + kGPad];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[kGT][kGK + kGPad];
     const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int kb = blockIdx.z * g.kslice;
+    const int ke = min(g.K, kb + g.kslice);
     f32x4m acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4m){0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += kGK) {
-        gemm_load_tile<A_KC>(g.A, g.lda, g.M, g.K, m0, k0, sA);
-        gemm_load_tile<B_KC>(g.B, g.ldb, g.N, g.K, n0, k0, sB);
+    Chunk<A_KC> ca;
+    Chunk<B_KC> cb;
+    if (kb < ke) {
+        ca.load(g.A, g.lda, g.M, g.K, m0, kb, g.vec_a);
+        cb.load(g.B, g.ldb, g.N, g.K, n0, kb, g.vec_b);
+    }
+    for (int k0 = kb; k0 < ke; k0 += kGK) {
+        ca.store(sA);
+        cb.store(sB);
         __syncthreads();
+        if (k0 + kGK < ke) {
+            ca.load(g.A, g.lda, g.M, g.K, m0, k0 + kGK, g.vec_a);
+            cb.load(g.B, g.ldb, g.N, g.K, n0, k0 + kGK, g.vec_b);
+        }
         const int kq = (lane >> 4) * 8, rl = lane & 15;
         bf16x8 a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) a[i][e] = sA[wm + 16 * i + rl][kq + e];
+            a[i] = *reinterpret_cast<const bf16x8 *>(&sA[wm + 16 * i + rl][kq]);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) b[j][e] = sB[wn + 16 * j + rl][kq + e];
+            b[j] = *reinterpret_cast<const bf16x8 *>(&sB[wn + 16 * j + rl][kq]);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -105,6 +159,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
         __syncthreads();
     }
     // D layout: lane holds rows 4*(lane/16) + r, column lane % 16 of each 16 x 16 block.
+    const bool split = gridDim.z > 1;
+    float *C = split ? g.C + (int64_t)blockIdx.z * g.M * g.ldc : g.C;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -115,22 +171,69 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
                 const int n = n0 + wn + 16 * j + (lane & 15);
                 if (m >= g.M || n >= g.N) continue;
                 float v = acc[i][j][r];
+                if (split) {
+                    C[(int64_t)m * g.ldc + n] = v;
+                    continue;
+                }
                 if (g.bias) v += g.bias[n];
                 if (g.relu) v = v > 0.f ? v : 0.f;
                 if (g.mask && !((float)g.mask[(int64_t)m * g.ldm + n] > 0.f)) v = 0.f;
-                if (g.C) g.C[(int64_t)m * g.ldc + n] = v;
+                if (g.C) C[(int64_t)m * g.ldc + n] = v;
                 if (g.Cb) g.Cb[(int64_t)m * g.ldcb + n] = (__bf16)v;
             }
 }
 
-static int gemm(const GemmArgs &g, bool a_kc, bool b_kc, hipStream_t s)
+// Sum of the split-K partial products in slice order (deterministic):
+// C[m][n] = sum_z part[z][m][n].
+__global__ void k_splitk_sum(const float *part, int32_t S, int32_t M, int32_t N, int64_t ldc,
+                             float *C)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)M * N) return;
+    const int64_t m = idx / N, n = idx - m * N;
+    float v = 0.0f;
+    for (int z = 0; z < S; ++z) v += part[(int64_t)z * M * ldc + m * ldc + n];
+    C[m * ldc + n] = v;
+}
+
+static bool vec_ok(const void *p, int64_t ld)
+{
+    return ((uintptr_t)p % 16) == 0 && (ld % 8) == 0;
+}
+
+// part: scratch for split-K partials (S * M * ldc floats) or null (no split).
+static int gemm(GemmArgs g, bool a_kc, bool b_kc, hipStream_t s, arsel_ctx *ctx = nullptr,
+                float *part = nullptr, size_t part_floats = 0)
 {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return ARSEL_OK;
-    dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT);
+    g.vec_a = vec_ok(g.A, g.lda);
+    g.vec_b = vec_ok(g.B, g.ldb);
+    dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT, 1);
+    g.kslice = g.K;
+    const bool plain = !g.bias && !g.relu && !g.mask && !g.Cb && g.C;
+    float *C_final = g.C;
+    int S = 1;
+    if (ctx && part && plain && g.K >= 256) {
+        const int tiles = (int)(grid.x * grid.y);
+        while (S < 8 && tiles * S * 2 <= 2 * ctx->num_cu && g.K / (S * 2) >= 128 &&
+               (size_t)(S * 2) * g.M * g.ldc <= part_floats)
+            S *= 2;
+    }
+    if (S > 1) {
+        g.kslice = ((g.K + S - 1) / S + kGK - 1) / kGK * kGK;
+        S = (g.K + g.kslice - 1) / g.kslice;
+        grid.z = S;
+        g.C = part;
+    }
     if (a_kc && b_kc) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, s, g);
     else if (a_kc) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, g);
     else if (b_kc) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, s, g);
     else hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, g);
+    if (S > 1) {
+        const int64_t n = (int64_t)g.M * g.N;
+        hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, S,
+                           g.M, g.N, g.ldc, C_final);
+    }
     return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
 }
 
@@ -403,7 +506,8 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
     for (int i = 0; i < 6; ++i)
         if (!tr->master[i] || !tr->grad[i] || !tr->m[i] || !tr->v[i]) return ARSEL_ERR_NULL;
     if ((rc = ctx_activate(ctx))) return rc;
-    const size_t extra = (size_t)B * (n->Mp * 6 + n->H * 12) + 8 * 256;
+    const size_t extra = (size_t)B * (n->Mp * 6 + n->H * 12) + 8 * 256 +
+                         (size_t)8 * std::max<size_t>((size_t)n->Mp * n->H, (size_t)n->H * n->Kp) * 4 + 256;
     if ((rc = ensure_ws(ctx, fwd_bytes(n, B) + extra))) return rc;
     hipStream_t s = (hipStream_t)stream;
     Carver cv{(char *)ctx->ws, 0};
@@ -415,6 +519,8 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
     float *dH2f = cv.take<float>((size_t)B * n->H);
     __bf16 *dH1 = cv.take<__bf16>((size_t)B * n->H);
     float *dH1f = cv.take<float>((size_t)B * n->H);
+    const size_t part_n = (size_t)8 * std::max<size_t>((size_t)n->Mp * n->H, (size_t)n->H * n->Kp);
+    float *part = cv.take<float>(part_n);
 
     hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, loss, (int64_t)1);
     const float scale = 1.0f / (float)B;
@@ -425,7 +531,7 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
     GemmArgs g = gemm_args(dZb, n->Mp, f.H2, n->H, n->Mp, n->H, B);     // dW3 = dZ^T H2
     g.C = tr->grad[4];
     g.ldc = n->H;
-    if ((rc = gemm(g, false, false, s))) return rc;
+    if ((rc = gemm(g, false, false, s, ctx, part, part_n))) return rc;
     hipLaunchKernelGGL(k_colsum, dim3((n->Mp + 63) / 64), dim3(1024), 0, s, dZf, (int64_t)n->Mp, B, n->Mp, tr->grad[5]);
     g = gemm_args(dZb, n->Mp, n->W3, n->H, B, n->H, n->Mp);              // dH2 = dZ W3 . [h2 > 0]
     g.mask = f.H2;
@@ -438,7 +544,7 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
     g = gemm_args(dH2, n->H, f.H1, n->H, n->H, n->H, B);                 // dW2 = dH2^T H1
     g.C = tr->grad[2];
     g.ldc = n->H;
-    if ((rc = gemm(g, false, false, s))) return rc;
+    if ((rc = gemm(g, false, false, s, ctx, part, part_n))) return rc;
     hipLaunchKernelGGL(k_colsum, dim3((n->H + 63) / 64), dim3(1024), 0, s, dH2f, (int64_t)n->H, B, n->H, tr->grad[3]);
     g = gemm_args(dH2, n->H, n->W2, n->H, B, n->H, n->H);                // dH1 = dH2 W2 . [h1 > 0]
     g.mask = f.H1;
@@ -451,7 +557,7 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
     g = gemm_args(dH1, n->H, f.F, n->Kp, n->H, n->Kp, B);                // dW1 = dH1^T F
     g.C = tr->grad[0];
     g.ldc = n->Kp;
-    if ((rc = gemm(g, false, false, s))) return rc;
+    if ((rc = gemm(g, false, false, s, ctx, part, part_n))) return rc;
     hipLaunchKernelGGL(k_colsum, dim3((n->H + 63) / 64), dim3(1024), 0, s, dH1f, (int64_t)n->H, B, n->H, tr->grad[1]);
 
     const int64_t sizes[6] = {(int64_t)n->H * n->Kp, n->H, (int64_t)n->H * n->H, n->H,

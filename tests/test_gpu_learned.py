@@ -27,9 +27,11 @@ def _bf16(shape, seed):
     return torch.randn(*shape, generator=g).to(torch.bfloat16)
 
 
+@pytest.mark.parametrize("shape", [(100, 70, 75), (256, 136, 96), (72, 64, 520)])
 @pytest.mark.parametrize("akc,bkc", [(True, True), (True, False), (False, True), (False, False)])
-def test_gemm_layouts(gpu, akc, bkc):
-    M, N, K = 100, 70, 75
+def test_gemm_layouts(gpu, akc, bkc, shape):
+    """Ragged edges (scalar loads), aligned tiles (16-byte loads) and a long K."""
+    M, N, K = shape
     A = _bf16((M, K) if akc else (K, M), 1)
     B = _bf16((N, K) if bkc else (K, N), 2)
     bias = torch.randn(N, generator=torch.Generator().manual_seed(3))
