@@ -65,6 +65,9 @@ def lib() -> ctypes.CDLL:
         L.orc_select_paper.restype = i32
         L.orc_select_ids.argtypes = [P, i64, i64, P, u64, u64, u32, P, P, P, i32]
         L.orc_select_ids.restype = i32
+        L.orc_ssa_run_proposal.argtypes = [P, i64, i64, i64, P, P, P, P, P, P, i64, P, u64, u64,
+                                           i64, u32, P, P, P, i32]
+        L.orc_ssa_run_proposal.restype = i32
         _lib = L
     return _lib
 
@@ -191,8 +194,9 @@ def ssa_chain(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: 
 
 
 def ssa_run(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: int = 4096,
-            t0=None, ids=None, want_times: bool = False, threads: int = 1):
-    """Full SSA run (direct method with the AR selection and the time step).
+            t0=None, ids=None, want_times: bool = False, threads: int = 1, Q=None):
+    """Full SSA run (direct method with the AR selection and the time step);
+    with Q ([R, M] uint32) the proposal AR selects, with Q'_j = max(Q_j, 1).
     Returns (X_final, t_final float64 [R], fired [steps, R], times or None)."""
     x = np.array(X0, dtype=np.int32, copy=True, order="C")
     R, N = x.shape
@@ -203,8 +207,14 @@ def ssa_run(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: in
     idv = None if ids is None else np.ascontiguousarray(ids, np.uint32)
     arrs = [np.ascontiguousarray(v, np.int32) for v in (net.r0, net.r1, net.p0, net.p1)]
     rate = np.ascontiguousarray(net.rate, np.float32)
-    lib().orc_ssa_run(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), _p(idv), seed, step0,
-                      steps, t_max, _p(t), _p(times), _p(fired), threads)
+    if Q is None:
+        lib().orc_ssa_run(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), _p(idv), seed, step0,
+                          steps, t_max, _p(t), _p(times), _p(fired), threads)
+    else:
+        q = np.ascontiguousarray(Q, dtype=np.uint32)
+        lib().orc_ssa_run_proposal(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), _p(q), M,
+                                   _p(idv), seed, step0, steps, t_max, _p(t), _p(times),
+                                   _p(fired), threads)
     return x, t, fired, times
 
 

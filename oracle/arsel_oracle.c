@@ -590,3 +590,61 @@ int orc_select_ids(const float *alpha, int64_t M, int64_t n, const uint32_t *ids
                                       t_max, alpha0 ? alpha0 + i : NULL, trials ? trials + i : NULL);
     return 0;
 }
+
+/* Full SSA run with an integer proposal (the learned proposal refreshed
+ * lazily, held fixed for the call): as orc_ssa_run, but each step selects
+ * with proposal AR (tag 1, instance id, step s) on the current propensities
+ * and Q'_j = max(Q_j, 1) for every j, so reactions that become active during
+ * the call stay covered.  Q is [R][ldq] uint32 (realization r's row). */
+int orc_ssa_run_proposal(int32_t *X, int64_t R, int64_t N, int64_t M,
+                         const int32_t *r0, const int32_t *r1, const int32_t *p0,
+                         const int32_t *p1, const float *rate, const uint32_t *Q, int64_t ldq,
+                         const uint32_t *ids, uint64_t seed, uint64_t step0, int64_t steps,
+                         uint32_t t_max, double *t, double *times, int32_t *fired, int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel if (threads != 1)
+#endif
+    {
+        float *a = (float *)malloc(sizeof(float) * (size_t)M);
+        uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)M);
+        uint32_t *prefix = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)M);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t r = 0; r < R; ++r) {
+            int32_t *x = X + r * N;
+            const uint32_t id = ids ? ids[r] : (uint32_t)r;
+            for (int64_t j = 0; j < M; ++j) {
+                const uint32_t v = Q[r * ldq + j];
+                q[j] = v > 0u ? v : 1u;
+            }
+            for (int64_t i = 0; i < steps; ++i) {
+                const uint64_t s = step0 + (uint64_t)i;
+                double a0 = 0.0;
+                for (int64_t j = 0; j < M; ++j) {
+                    a[j] = mass_action(x, r0[j], r1[j], rate[j]);
+                    a0 += (double)a[j];
+                }
+                int32_t j = select_proposal_one(a, q, M, id, seed, s, t_max, NULL, prefix);
+                if (fired) fired[i * R + r] = j;
+                if (j >= 0) {
+                    uint32_t w[4];
+                    draw(seed, TAU_BLOCK, id, s, 2u, w);
+                    const double u = ((double)w[0] + 0.5) * 0x1p-32;
+                    t[r] += log(1.0 / u) / a0;
+                    x[r0[j]] -= 1;
+                    if (r1[j] >= 0) x[r1[j]] -= 1;
+                    x[p0[j]] += 1;
+                    if (p1[j] >= 0) x[p1[j]] += 1;
+                }
+                if (times) times[i * R + r] = t[r];
+            }
+        }
+        free(a);
+        free(q);
+        free(prefix);
+    }
+    return 0;
+}

@@ -6,6 +6,7 @@ import numpy as np
 from scipy import stats
 
 import oracle
+from oracle import laws
 from paper_1404_0027_amd import workloads
 
 
@@ -58,3 +59,28 @@ def test_instance_ids_select_the_stream():
     x2, t2, f2, _ = oracle.ssa_run(net, X0[ids], seed=3, step0=0, steps=40, ids=ids)
     assert np.array_equal(x2, x[ids]) and np.array_equal(t2, t[ids])
     assert np.array_equal(f2, f[:, ids])
+
+
+def test_run_with_a_proposal_keeps_the_direct_method_laws():
+    """With any proposal covering every reaction the run is the direct method:
+    the pure-decay absorption-time law holds and first selections follow
+    alpha_j / alpha_0 whatever Q is."""
+    n, k, R = 6, 0.5, 20000
+    net = _decay_net(k)
+    X0 = np.tile(np.array([[n, 0]], np.int32), (R, 1))
+    Q = np.full((R, 1), 7, np.uint32)
+    x, t, fired, _ = oracle.ssa_run(net, X0, seed=11, step0=0, steps=n + 2, threads=8, Q=Q)
+    assert np.all(x == np.array([0, n])) and np.all(fired[n:] == -1)
+    i = np.arange(1, n + 1)
+    mean, var = np.sum(1.0 / (k * i)), np.sum(1.0 / (k * i) ** 2)
+    assert abs(t.mean() - mean) < 5.0 * np.sqrt(var / R)
+    # first selection from one state under a deliberately poor proposal
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    R = 60000
+    X0 = np.tile(workloads.poisson_counts(N=64, R=1, seed=5), (R, 1))
+    rng = np.random.default_rng(1)
+    Q = np.tile(rng.integers(0, 50, size=(1, 100)).astype(np.uint32), (R, 1))   # zeros allowed
+    _, _, f, _ = oracle.ssa_run(net, X0, seed=4, step0=0, steps=1, threads=8, Q=Q)
+    a = oracle.propensities(net, X0[:1])[0].astype(np.float64)
+    counts = np.bincount(f[0], minlength=100)
+    assert laws.chi_square_p(counts, a / a.sum()) > 0.01
