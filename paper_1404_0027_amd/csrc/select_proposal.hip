@@ -10,7 +10,7 @@
 // alpha_j whatever Q is: the law stays alpha_j / alpha_0.  After t_max rejected
 // trials the same fixed-point inverse transform as the uniform path runs.
 #include "launch.hpp"
-#include "select_core.hpp"
+#include "proposal_core.hpp"
 
 namespace arsel {
 
@@ -24,17 +24,6 @@ struct PropArgs {
     int32_t *index;
     uint32_t *trials;
 };
-
-__device__ __forceinline__ double wave_max_f64(double x)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint64_t b = (uint64_t)__double_as_longlong(x);
-        const uint64_t o = shfl_xor_u64(b, off);
-        x = fmax(x, __longlong_as_double((long long)o));
-    }
-    return x;
-}
 
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_select_proposal(PropArgs a)
@@ -75,36 +64,8 @@ __global__ __launch_bounds__(NW * 64) void k_select_proposal(PropArgs a)
     } else {
         wave_scan(ContigAcc{sa}, M, amax, bad);
     }
-    // c = max over the support of fl64(alpha_j / Q_j).  Rounding is monotone,
-    // so c is fl64 of the largest exact ratio: a float estimate of each ratio
-    // (relative error < 2^-22 while the largest is above 2^-100) keeps every
-    // index within 2^-19 of the largest estimate, which contains the argmax,
-    // and only those get the binary64 division.  Tiny ratios take the exact
-    // loop over all indices.
     bool miss = false;
-    float rmax = 0.0f;
-    for (uint32_t j = lane; j < M; j += kWave) {
-        const float x = sa[j];
-        if (x > 0.0f) {
-            const uint32_t q = sq[j];
-            if (q == 0)
-                miss = true;
-            else
-                rmax = fmaxf(rmax, x / (float)q);
-        }
-    }
-    miss = __ballot(miss) != 0;
-    rmax = wave_max(rmax);
-    const bool fast = rmax >= 0x1p-100f;
-    const float thr = rmax - rmax * 0x1p-19f;
-    double c = 0.0;
-    for (uint32_t j = lane; j < M; j += kWave) {
-        const float x = sa[j];
-        const uint32_t q = sq[j];
-        if (x > 0.0f && q != 0 && (!fast || x / (float)q >= thr))
-            c = fmax(c, (double)x / (double)q);
-    }
-    c = wave_max_f64(c);
+    const double c = wave_proposal_c(sa, M, [&](uint32_t j) { return sq[j]; }, miss);
     Outcome o;
     o.trials = 0;
     if (bad)
@@ -114,73 +75,10 @@ __global__ __launch_bounds__(NW * 64) void k_select_proposal(PropArgs a)
     else if (miss || sumq >= (1ull << 32))
         o.index = -4;
     else {
-        // inclusive prefix of Q (exact: sum Q < 2^32): lane l owns the
-        // contiguous range [l per, (l + 1) per), one DPP scan of the range sums
-        {
-            const uint32_t per = (M + kWave - 1) / kWave;
-            const uint32_t lo = min((uint32_t)lane * per, M), hi = min(lo + per, M);
-            uint32_t part = 0;
-            for (uint32_t j = lo; j < hi; ++j) part += sq[j];
-            uint32_t run = wave_incl_scan_u32(part) - part;
-            for (uint32_t j = lo; j < hi; ++j) {
-                run += sq[j];
-                sp[j] = run;          // in place: sp aliases sq
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint32_t S = (uint32_t)sumq;
-        const uint32_t thresh = lemire_threshold(S);
+        wave_prefix_u32([&](uint32_t j) { return sq[j]; }, sp, M);   // in place: sp aliases sq
         const double cplus = __longlong_as_double(__double_as_longlong(c) + 1);   // nextafter up
         const Stream st = make_stream(a.seed, a.step, (uint32_t)k, kTagProposal);
-        const uint32_t rounds = (uint32_t)(((uint64_t)a.t_max + kRoundTrials - 1) / kRoundTrials);
-        auto pick = [&](uint32_t V) {
-            uint32_t lo = 0, hi = M - 1;   // least j with P_j > V
-            while (lo < hi) {
-                const uint32_t mid = lo + ((hi - lo) >> 1);
-                if (sp[mid] > V)
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            return lo;
-        };
-        auto accept = [&](uint32_t j, uint32_t uw) {
-            const double uc = grid_u(uw) * cplus;
-            const uint32_t qj = sp[j] - (j ? sp[j - 1] : 0u);
-            return uc * (double)qj < (double)sa[j];
-        };
-        uint64_t key = kNoAccept;
-        for (uint32_t r = 0; r < rounds && key == kNoAccept; r = uniform_u32(r + 1)) {
-            const uint64_t t0 = (uint64_t)r * kRoundTrials;
-            const Words w = st.block((uint32_t)(t0 >> 1) + (uint32_t)lane);
-            const uint64_t ta = t0 + 2 * (uint64_t)lane;
-            uint32_t va, vb;
-            const bool oka = lemire(w.w0, S, thresh, va) && ta < a.t_max;
-            const bool okb = lemire(w.w2, S, thresh, vb) && ta + 1 < a.t_max;
-            const uint32_t ja = pick(va), jb = pick(vb);
-            const bool acca = oka && accept(ja, w.w1);
-            const bool accb = okb && accept(jb, w.w3);
-            const uint64_t ma = __ballot(acca), mb = __ballot(accb);
-            if (ma | mb) {
-                const int la = first_lane(ma), lb = first_lane(mb);
-                key = la <= lb ? ((t0 + 2 * (uint64_t)la) << 32) | readlane_u32(ja, la)
-                               : ((t0 + 2 * (uint64_t)lb + 1) << 32) | readlane_u32(jb, lb);
-            }
-        }
-        if (key != kNoAccept) {
-            o.index = (int32_t)(uint32_t)key;
-            o.trials = (uint32_t)(key >> 32) + 1;
-        } else {
-            const int shift = 63 - ceil_log2_u32(M) - exponent_above(amax);
-            const ContigAcc acc{sa};
-            const uint64_t Sf = wave_fixed_sum(acc, M, shift);
-            const Words w = st.block(kFallbackBlock);
-            const uint64_t V = (uint64_t)w.w0 | ((uint64_t)w.w1 << 32);
-            o.index = wave_fixed_search(acc, M, shift, umul64hi(V, Sf));
-            o.trials = a.t_max + 1;
-        }
+        o = wave_proposal_rounds(sa, sp, M, (uint32_t)sumq, cplus, amax, st, a.t_max);
     }
     if (lane == 0) {
         a.index[k] = o.index;

@@ -174,3 +174,30 @@ def test_million_realizations_sampled(gpu):
     assert np.array_equal(idx.cpu().numpy()[ids], oi)
     assert np.array_equal(tr.cpu().numpy().view(np.uint32)[ids], ot)
     assert np.array_equal(a0.cpu().numpy()[ids].view(np.uint32), oa.view(np.uint32))
+
+
+def test_graph_replays_match_eager(gpu):
+    """The bench captures its steps in a HIP graph: replays (with eager work
+    and synchronisation between them) give the eager results, step by step."""
+    M, K, steps = 1029, 4096, 6
+    host = workloads.lognormal_soa(M=M, K=K, seed=2, buffers=3)
+    bufs = torch.from_numpy(host).cuda()
+    out = torch.empty(steps, K, dtype=torch.int32, device="cuda")
+    eager = torch.empty_like(out)
+    for s in range(steps):
+        arsel.select(bufs[s % 3], M, K, K, SOA, seed=1, step=s, index=eager[s])
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(g, stream=cap, capture_error_mode="relaxed"):
+            for s in range(steps):
+                arsel.select(bufs[s % 3], M, K, K, SOA, seed=1, step=s, index=out[s])
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        arsel.select(bufs[0], M, K, K, SOA, seed=9, step=99, index=eager[0].clone())   # eager work between
