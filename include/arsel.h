@@ -246,6 +246,23 @@ int arsel_ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
                   int64_t steps, uint32_t t_max, double *t, double *times, int32_t *fired,
                   void *stream);
 
+/* The full SSA run selecting with an integer proposal (the learned proposal of
+ * the neural-network extension, refreshed lazily by the caller between
+ * calls): as arsel_ssa_run, except that each step selects as
+ * arsel_select_proposal does (tag-1 stream, instance r, step step0 + i) with
+ * Q'_j = max(Q_j, 1), Q the DEVICE uint32 row [r][ldq] of realization r
+ * (ldq >= M, held fixed for the call).  Q' is positive everywhere, so a
+ * reaction that becomes active during the call stays covered and each step's
+ * law is alpha_j / alpha_0; c = max_j fl64(alpha_j / Q'_j) is recomputed
+ * exactly every step.  A realization with sum Q' >= 2^32 records -4 at every
+ * step and does not move.  Q NULL: ARSEL_ERR_NULL; ldq < M: ARSEL_ERR_LD;
+ * (N + 2 M) * 4 bytes above one workgroup's LDS: ARSEL_ERR_SIZE. */
+int arsel_ssa_run_proposal(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
+                           const int32_t *ndeps, const uint32_t *Q, int64_t ldq, int32_t *X,
+                           int32_t R, uint64_t seed, uint64_t step0, int64_t steps,
+                           uint32_t t_max, double *t, double *times, int32_t *fired,
+                           void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned proposal (BF16 MLP on MFMA, FP32 accumulation).
  *

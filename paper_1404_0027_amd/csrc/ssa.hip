@@ -11,6 +11,7 @@
 // it, so they are not drawn.  Step i of realization r selects with uniform
 // acceptance-rejection on the tag-2 stream (instance r, step step0 + i).
 #include "launch.hpp"
+#include "proposal_core.hpp"
 #include "select_core.hpp"
 
 namespace arsel {
@@ -146,15 +147,21 @@ struct RunArgs {
     double *t;           // [R], advanced in place
     double *times;       // [steps][R] or null
     int32_t *fired;      // [steps][R] or null
+    const uint32_t *Q;   // [R][ldq] integer proposal (proposal run only)
+    int64_t ldq;
 };
 
 // One wavefront per realization, counts and propensities in its LDS.  Each
 // step: exact alpha_max (bit maximum) and alpha_0 over the propensities, the
-// AR selection on the tag-2 stream (the jump chain's), tau = ln(1/u) /
-// alpha_0 with u from Philox block 0xFFFFFFFE of that stream, the
-// stoichiometry, and the propensities of the reactions the fired one
-// affects.  A step with nothing able to fire leaves state and time.
-template <int NW>
+// AR selection, tau = ln(1/u) / alpha_0 with u from Philox block 0xFFFFFFFE
+// of the tag-2 stream, the stoichiometry, and the propensities of the
+// reactions the fired one affects.  A step with nothing able to fire leaves
+// state and time.  PROP = false selects with uniform AR on the tag-2 stream
+// (the jump chain's); PROP = true with the integer proposal Q'_j =
+// max(Q_j, 1) of the realization (its inclusive prefix kept in LDS for the
+// whole call) on the tag-1 stream, with c = max_j fl64(alpha_j / Q'_j)
+// recomputed exactly every step, so every step's law is alpha_j / alpha_0.
+template <int NW, bool PROP>
 __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
 {
     extern __shared__ int32_t lds_i[];
@@ -163,11 +170,23 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
     const int r = blockIdx.x * NW + wave;
     if (r >= c.R) return;
     const int N = c.net.N, M = c.net.M;
-    int32_t *x = lds_i + (size_t)wave * (N + M);
+    int32_t *x = lds_i + (size_t)wave * (N + (PROP ? 2 : 1) * M);
     float *a = reinterpret_cast<float *>(x + N);
+    uint32_t *sp = reinterpret_cast<uint32_t *>(a + M);   // prefix of Q' (PROP)
     int32_t *gx = c.X + (int64_t)r * N;
     for (int i = lane; i < N; i += kWave) x[i] = gx[i];
+    uint64_t sumq = 0;
+    if (PROP) {
+        const uint32_t *gq = c.Q + (int64_t)r * c.ldq;
+        for (int j = lane; j < M; j += kWave) {
+            const uint32_t q = max(gq[j], 1u);
+            sp[j] = q;
+            sumq += q;
+        }
+        sumq = wave_sum_u64(sumq);
+    }
     wave_sync_lds();
+    if (PROP) wave_prefix_u32([&](uint32_t j) { return sp[j]; }, sp, (uint32_t)M);
     for (int j = lane; j < M; j += kWave) a[j] = mass_action(x, c.net.r0[j], c.net.r1[j], c.net.rate[j]);
     wave_sync_lds();
     double t = c.t[r];
@@ -183,7 +202,33 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
         mb = wave_max_u32(mb);
         a0 = wave_sum_f64(a0);
         const Stream st = make_stream(c.seed, s, (uint32_t)r, kTagSSA);
-        const Outcome o = wave_select_hint(ContigAcc{a}, (uint32_t)M, mb, st, c.t_max, false);
+        Outcome o;
+        if (PROP) {
+            float amax;
+            bool bad;
+            if (mb < 0x7F800000u) {
+                amax = __uint_as_float(mb);
+                bad = false;
+            } else {
+                wave_scan(ContigAcc{a}, (uint32_t)M, amax, bad);
+            }
+            if (bad)
+                o.index = -2;
+            else if (amax == 0.0f)
+                o.index = -1;
+            else if (sumq >= (1ull << 32))
+                o.index = -4;
+            else {
+                bool miss;   // never set: Q' >= 1 everywhere
+                const double cq = wave_proposal_c(
+                    a, (uint32_t)M, [&](uint32_t jj) { return sp[jj] - (jj ? sp[jj - 1] : 0u); }, miss);
+                const double cplus = __longlong_as_double(__double_as_longlong(cq) + 1);
+                const Stream sq = make_stream(c.seed, s, (uint32_t)r, kTagProposal);
+                o = wave_proposal_rounds(a, sp, (uint32_t)M, (uint32_t)sumq, cplus, amax, sq, c.t_max);
+            }
+        } else {
+            o = wave_select_hint(ContigAcc{a}, (uint32_t)M, mb, st, c.t_max, false);
+        }
         const int32_t j = (int32_t)uniform_u32((uint32_t)o.index);
         if (c.fired && lane == 0) c.fired[i * c.R + r] = j;
         if (j >= 0) {
@@ -282,25 +327,61 @@ extern "C" int arsel_ssa_deps(arsel_ctx *ctx, const arsel_network *net, int32_t 
     return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
 }
 
-extern "C" int arsel_ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
-                             const int32_t *ndeps, int32_t *X, int32_t R, uint64_t seed,
-                             uint64_t step0, int64_t steps, uint32_t t_max, double *t,
-                             double *times, int32_t *fired, void *stream)
+namespace arsel {
+
+static int ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
+                   const int32_t *ndeps, const uint32_t *Q, int64_t ldq, int32_t *X, int32_t R,
+                   uint64_t seed, uint64_t step0, int64_t steps, uint32_t t_max, double *t,
+                   double *times, int32_t *fired, void *stream)
 {
     if (!ctx) return ARSEL_ERR_NULL;
     int rc = check_net(net);
     if (rc) return rc;
     if (R < 0 || steps < 0) return ARSEL_ERR_SIZE;
+    const bool prop = Q != nullptr;
+    if (prop && ldq < net->M) return ARSEL_ERR_LD;
     if (R == 0 || steps == 0) return ARSEL_OK;
     if (!deps || !ndeps || !X || !t) return ARSEL_ERR_NULL;
     if ((rc = ctx_activate(ctx))) return rc;
-    const size_t per_wave = (size_t)(net->N + net->M) * 4;
+    const size_t per_wave = (size_t)(net->N + (prop ? 2 : 1) * (size_t)net->M) * 4;
     if (per_wave > ctx->lds_per_block) return ARSEL_ERR_SIZE;
-    RunArgs c{net_args(net), deps, ndeps, X, R, seed, step0, steps, t_max, t, times, fired};
+    RunArgs c{net_args(net), deps, ndeps, X, R, seed, step0, steps, t_max, t, times, fired, Q, ldq};
     hipStream_t s = (hipStream_t)stream;
-    if (per_wave * 4 <= ctx->tile_lds_bytes)
-        hipLaunchKernelGGL(k_ssa_run<4>, dim3((R + 3) / 4), dim3(256), per_wave * 4, s, c);
-    else
-        hipLaunchKernelGGL(k_ssa_run<1>, dim3(R), dim3(64), per_wave, s, c);
+    const bool four = per_wave * 4 <= ctx->tile_lds_bytes;
+    const dim3 grid(four ? (R + 3) / 4 : R), block(four ? 256 : 64);
+    const size_t lds = per_wave * (four ? 4 : 1);
+    if (prop) {
+        if (four)
+            hipLaunchKernelGGL((k_ssa_run<4, true>), grid, block, lds, s, c);
+        else
+            hipLaunchKernelGGL((k_ssa_run<1, true>), grid, block, lds, s, c);
+    } else {
+        if (four)
+            hipLaunchKernelGGL((k_ssa_run<4, false>), grid, block, lds, s, c);
+        else
+            hipLaunchKernelGGL((k_ssa_run<1, false>), grid, block, lds, s, c);
+    }
     return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
+
+}  // namespace arsel
+
+extern "C" int arsel_ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
+                             const int32_t *ndeps, int32_t *X, int32_t R, uint64_t seed,
+                             uint64_t step0, int64_t steps, uint32_t t_max, double *t,
+                             double *times, int32_t *fired, void *stream)
+{
+    return arsel::ssa_run(ctx, net, deps, ndeps, nullptr, 0, X, R, seed, step0, steps, t_max, t,
+                          times, fired, stream);
+}
+
+extern "C" int arsel_ssa_run_proposal(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
+                                      const int32_t *ndeps, const uint32_t *Q, int64_t ldq,
+                                      int32_t *X, int32_t R, uint64_t seed, uint64_t step0,
+                                      int64_t steps, uint32_t t_max, double *t, double *times,
+                                      int32_t *fired, void *stream)
+{
+    if (!Q) return ARSEL_ERR_NULL;
+    return arsel::ssa_run(ctx, net, deps, ndeps, Q, ldq, X, R, seed, step0, steps, t_max, t,
+                          times, fired, stream);
 }

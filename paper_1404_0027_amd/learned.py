@@ -73,19 +73,32 @@ class DeviceNetwork:
         return self._deps
 
     def run(self, X: torch.Tensor, t: torch.Tensor, *, seed: int, step0: int, steps: int,
-            t_max: int = 4096, want_fired: bool = False, want_times: bool = False):
+            t_max: int = 4096, want_fired: bool = False, want_times: bool = False, Q=None):
         """Full SSA run in place on X [R, N] (int32) and t [R] (float64);
-        returns (fired [steps, R] or None, times [steps, R] or None)."""
+        with Q ([R, ldq] int32/uint32 proposal, ldq >= M) the steps select
+        with the proposal Q' = max(Q, 1).  Returns (fired [steps, R] or None,
+        times [steps, R] or None)."""
         R = X.shape[0]
         arsel._need(X, torch.int32, R * self.N, "X", self.device)
         arsel._need(t, torch.float64, R, "t", self.device)
         d, n = self.deps()
         fired = torch.empty(steps, R, dtype=torch.int32, device=self.device) if want_fired else None
         times = torch.empty(steps, R, dtype=torch.float64, device=self.device) if want_times else None
-        rc = lib().arsel_ssa_run(context(self.device), ctypes.byref(self.c), _ptr(d), _ptr(n),
-                                 _ptr(X), R, seed & (2**64 - 1), step0 & (2**64 - 1), steps, t_max,
-                                 _ptr(t), _ptr(times), _ptr(fired), _stream(self.device))
-        _check(rc, "arsel_ssa_run")
+        common = (_ptr(X), R, seed & (2**64 - 1), step0 & (2**64 - 1), steps, t_max, _ptr(t),
+                  _ptr(times), _ptr(fired), _stream(self.device))
+        if Q is None:
+            rc = lib().arsel_ssa_run(context(self.device), ctypes.byref(self.c), _ptr(d), _ptr(n),
+                                     *common)
+            _check(rc, "arsel_ssa_run")
+        else:
+            if Q.dim() != 2 or Q.shape[0] != R or Q.shape[1] < self.M:
+                raise arsel.ArselError("Q must be [R, ldq] with ldq >= M")
+            if Q.dtype not in (torch.int32, torch.uint32):
+                raise arsel.ArselError("Q must be int32 or uint32")
+            arsel._need(Q, Q.dtype, Q.numel(), "Q", self.device)
+            rc = lib().arsel_ssa_run_proposal(context(self.device), ctypes.byref(self.c), _ptr(d),
+                                              _ptr(n), _ptr(Q), Q.shape[1], *common)
+            _check(rc, "arsel_ssa_run_proposal")
         return fired, times
 
 

@@ -108,3 +108,116 @@ def test_run_full_size_sampled(gpu):
     assert np.array_equal(X.cpu().numpy()[ids], xo)
     np.testing.assert_allclose(t.cpu().numpy()[ids], to, rtol=1e-9, atol=0)
     assert np.array_equal(X.cpu().numpy().sum(axis=1), X0.sum(axis=1))
+
+
+# ---- the run with an integer proposal (Q' = max(Q, 1), tag-1 stream) ----
+
+def _shaped_q(net, X0):
+    """A proposal shaped like the initial propensities (what a trained
+    network approximates): alpha quantised to 16 bits of its row maximum,
+    zero where the reaction is inactive."""
+    a = oracle.propensities(net, X0).astype(np.float64)
+    amax = a.max(axis=1, keepdims=True)
+    return np.floor(a / np.where(amax > 0, amax, 1.0) * 65535.0).astype(np.uint32)
+
+
+def _run_both_q(net, X0, Q, *, seed, step0, steps, t_max=4096, ldq=None, want_times=True):
+    R, M = Q.shape
+    ldq = ldq or M
+    Qp = np.zeros((R, ldq), np.uint32)
+    Qp[:, :M] = Q
+    Qp[:, M:] = 0xDEADBEEF                      # padding is never read
+    dn = learned.DeviceNetwork(net)
+    X = torch.from_numpy(X0).cuda()
+    t = torch.zeros(R, dtype=torch.float64, device="cuda")
+    Qd = torch.from_numpy(Qp.view(np.int32)).cuda()
+    fired, times = dn.run(X, t, seed=seed, step0=step0, steps=steps, t_max=t_max, want_fired=True,
+                          want_times=want_times, Q=Qd)
+    xo, to, fo, tmo = oracle.ssa_run(net, X0, seed=seed, step0=step0, steps=steps, t_max=t_max,
+                                     want_times=want_times, threads=8, Q=Q)
+    assert np.array_equal(fired.cpu().numpy(), fo)
+    assert np.array_equal(X.cpu().numpy(), xo)
+    np.testing.assert_allclose(t.cpu().numpy(), to, rtol=1e-12, atol=0)
+    if want_times:
+        np.testing.assert_allclose(times.cpu().numpy(), tmo, rtol=1e-12, atol=0)
+    return fo
+
+
+@pytest.mark.parametrize("kind", ["random", "shaped"])
+@pytest.mark.parametrize("N,M,R,steps", [(64, 100, 40, 300), (641, 1029, 64, 200)])
+def test_run_with_proposal_matches_oracle(gpu, N, M, R, steps, kind):
+    net = workloads.mass_action_network(N=N, M=M, seed=4)
+    X0 = workloads.poisson_counts(N=N, R=R, seed=5)
+    if kind == "random":
+        rng = np.random.default_rng(M)
+        Q = rng.integers(0, 1000, size=(R, M)).astype(np.uint32)
+        Q[rng.random((R, M)) < 0.2] = 0
+    else:
+        Q = _shaped_q(net, X0)
+    _run_both_q(net, X0, Q, seed=3, step0=11, steps=steps)
+
+
+@pytest.mark.parametrize("t_max", [0, 1, 3])
+def test_run_with_proposal_budgets_and_padding(gpu, t_max):
+    """Short trial budgets (fallback inverse transform) and ldq > M."""
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    X0 = workloads.poisson_counts(N=64, R=48, seed=7)
+    Q = _shaped_q(net, X0)
+    _run_both_q(net, X0, Q, seed=5, step0=2, steps=120, t_max=t_max, ldq=107)
+
+
+def test_run_with_proposal_overflow_and_absorption(gpu):
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    X0 = workloads.poisson_counts(N=64, R=32, seed=8)
+    Q = _shaped_q(net, X0)
+    Q[:10] = 0xFFFFFFFF                         # sum Q' >= 2^32: -4, nothing moves
+    fo = _run_both_q(net, X0, Q, seed=6, step0=0, steps=50)
+    assert np.all(fo[:, :10] == -4) and np.all(fo[:, 10:] >= 0)
+    dec = workloads.Network(N=2, r0=np.array([0], np.int32), r1=np.array([-1], np.int32),
+                            p0=np.array([1], np.int32), p1=np.array([-1], np.int32),
+                            rate=np.array([0.5], np.float32))
+    X0 = np.tile(np.array([[5, 0]], np.int32), (64, 1))
+    fo = _run_both_q(dec, X0, np.zeros((64, 1), np.uint32), seed=1, step0=0, steps=9)
+    assert np.all(fo[:5] == 0) and np.all(fo[5:] == -1)
+
+
+def test_run_with_proposal_argument_errors(gpu):
+    import ctypes
+
+    from paper_1404_0027_amd import arsel
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    dn = learned.DeviceNetwork(net)
+    d, n = dn.deps()
+    X = torch.from_numpy(workloads.poisson_counts(N=64, R=4, seed=1)).cuda()
+    t = torch.zeros(4, dtype=torch.float64, device="cuda")
+    Q = torch.ones(4, 100, dtype=torch.int32, device="cuda")
+    call = lambda q, ldq: arsel.lib().arsel_ssa_run_proposal(
+        arsel.context(0), ctypes.byref(dn.c), d.data_ptr(), n.data_ptr(), q, ldq, X.data_ptr(), 4,
+        1, 0, 5, 4096, t.data_ptr(), None, None, torch.cuda.current_stream().cuda_stream)
+    assert call(None, 100) == -1                  # Q NULL
+    assert call(Q.data_ptr(), 99) == -4           # ldq < M
+    assert call(Q.data_ptr(), 100) == 0
+    with pytest.raises(arsel.ArselError):
+        dn.run(X, t, seed=1, step0=0, steps=1, Q=Q[:, :99].contiguous())
+
+
+def test_run_with_proposal_full_size_sampled(gpu):
+    """R = 16384 x 10^4 steps with the proposal shaped on the initial states;
+    four realizations replayed by the oracle (instance ids kept)."""
+    net = workloads.mass_action_network()
+    R, steps = 16384, 10000
+    X0 = workloads.poisson_counts(N=net.N, R=R, seed=5)
+    ids = np.array([0, 777, 9999, R - 1], np.uint32)
+    Q = np.zeros((R, net.M), np.uint32)
+    Q[ids] = _shaped_q(net, X0[ids])
+    Q[np.setdiff1d(np.arange(R), ids)] = 3
+    dn = learned.DeviceNetwork(net)
+    X = torch.from_numpy(X0).cuda()
+    t = torch.zeros(R, dtype=torch.float64, device="cuda")
+    dn.run(X, t, seed=7, step0=0, steps=steps, Q=torch.from_numpy(Q.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    xo, to, _, _ = oracle.ssa_run(net, X0[ids], seed=7, step0=0, steps=steps, ids=ids, threads=4,
+                                  Q=Q[ids])
+    assert np.array_equal(X.cpu().numpy()[ids], xo)
+    np.testing.assert_allclose(t.cpu().numpy()[ids], to, rtol=1e-9, atol=0)
+    assert np.array_equal(X.cpu().numpy().sum(axis=1), X0.sum(axis=1))
