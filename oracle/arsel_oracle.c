@@ -594,11 +594,13 @@ int orc_select_ids(const float *alpha, int64_t M, int64_t n, const uint32_t *ids
 /* Full SSA run with an integer proposal (the learned proposal refreshed
  * lazily, held fixed for the call): as orc_ssa_run, but each step selects
  * with proposal AR (tag 1, instance id, step s) on the current propensities
- * and Q'_j = max(Q_j, 1) for every j, so reactions that become active during
- * the call stay covered.  Q is [R][ldq] uint32 (realization r's row). */
+ * and Q'_j = max(Q_j, qfloor, 1) for every j, so reactions that become active
+ * during the call stay covered, with a weight the caller sizes against the
+ * scale of Q.  Q is [R][ldq] uint32 (realization r's row). */
 int orc_ssa_run_proposal(int32_t *X, int64_t R, int64_t N, int64_t M,
                          const int32_t *r0, const int32_t *r1, const int32_t *p0,
                          const int32_t *p1, const float *rate, const uint32_t *Q, int64_t ldq,
+                         uint32_t qfloor,
                          const uint32_t *ids, uint64_t seed, uint64_t step0, int64_t steps,
                          uint32_t t_max, double *t, double *times, int32_t *fired, int threads)
 {
@@ -616,9 +618,10 @@ int orc_ssa_run_proposal(int32_t *X, int64_t R, int64_t N, int64_t M,
         for (int64_t r = 0; r < R; ++r) {
             int32_t *x = X + r * N;
             const uint32_t id = ids ? ids[r] : (uint32_t)r;
+            const uint32_t lo = qfloor > 0u ? qfloor : 1u;
             for (int64_t j = 0; j < M; ++j) {
                 const uint32_t v = Q[r * ldq + j];
-                q[j] = v > 0u ? v : 1u;
+                q[j] = v > lo ? v : lo;
             }
             for (int64_t i = 0; i < steps; ++i) {
                 const uint64_t s = step0 + (uint64_t)i;

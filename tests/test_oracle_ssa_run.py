@@ -84,3 +84,19 @@ def test_run_with_a_proposal_keeps_the_direct_method_laws():
     a = oracle.propensities(net, X0[:1])[0].astype(np.float64)
     counts = np.bincount(f[0], minlength=100)
     assert laws.chi_square_p(counts, a / a.sum()) > 0.01
+
+
+def test_proposal_floor_is_a_plain_maximum():
+    """Q'_j = max(Q_j, qfloor, 1): a floor below every Q changes nothing, and a
+    floor above every Q replaces all of them (not added to them)."""
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    X0 = workloads.poisson_counts(N=64, R=16, seed=5)
+    rng = np.random.default_rng(2)
+    Q = rng.integers(50, 400, size=(16, 100)).astype(np.uint32)
+    a = oracle.ssa_run(net, X0, seed=3, step0=0, steps=40, Q=Q)[2]
+    b = oracle.ssa_run(net, X0, seed=3, step0=0, steps=40, Q=Q, qfloor=50)[2]
+    assert np.array_equal(a, b)
+    c = oracle.ssa_run(net, X0, seed=3, step0=0, steps=40, Q=Q, qfloor=400)[2]
+    d = oracle.ssa_run(net, X0, seed=3, step0=0, steps=40, Q=np.full_like(Q, 400))[2]
+    e = oracle.ssa_run(net, X0, seed=3, step0=0, steps=40, Q=Q + 400)[2]
+    assert np.array_equal(c, d) and not np.array_equal(c, e)
