@@ -58,15 +58,15 @@ def lib() -> ctypes.CDLL:
         L.orc_ssa_chain.argtypes = [P, i64, i64, i64, P, P, P, P, P, u64, u64, i64, u32, i64,
                                     P, P, i32]
         L.orc_ssa_chain.restype = i32
-        L.orc_ssa_run.argtypes = [P, i64, i64, i64, P, P, P, P, P, P, u64, u64, i64, u32, P, P,
-                                  P, i32]
+        L.orc_ssa_run.argtypes = [P, i64, i64, i64, P, P, P, P, P, u32, P, u64, u64, i64, u32, P,
+                                  P, P, i32]
         L.orc_ssa_run.restype = i32
         L.orc_select_paper.argtypes = [P, i64, i64, i64, ctypes.c_double, u64, u64, P, i32]
         L.orc_select_paper.restype = i32
         L.orc_select_ids.argtypes = [P, i64, i64, P, u64, u64, u32, P, P, P, i32]
         L.orc_select_ids.restype = i32
-        L.orc_ssa_run_proposal.argtypes = [P, i64, i64, i64, P, P, P, P, P, P, i64, u32, P, u64,
-                                           u64, i64, u32, P, P, P, i32]
+        L.orc_ssa_run_proposal.argtypes = [P, i64, i64, i64, P, P, P, P, P, P, i64, u32, u32, P,
+                                           u64, u64, i64, u32, P, P, P, i32]
         L.orc_ssa_run_proposal.restype = i32
         _lib = L
     return _lib
@@ -195,10 +195,11 @@ def ssa_chain(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: 
 
 def ssa_run(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: int = 4096,
             t0=None, ids=None, want_times: bool = False, threads: int = 1, Q=None,
-            qfloor: int = 1):
+            qfloor: int = 1, period: int = 1):
     """Full SSA run (direct method with the AR selection and the time step);
     with Q ([R, M] uint32) the proposal AR selects, with
-    Q'_j = max(Q_j, qfloor, 1).
+    Q'_j = max(Q_j, qfloor, 1).  period p: the envelopes are exact at the
+    call's first step and at steps s with s mod p = 0, running maxima between.
     Returns (X_final, t_final float64 [R], fired [steps, R], times or None)."""
     x = np.array(X0, dtype=np.int32, copy=True, order="C")
     R, N = x.shape
@@ -210,13 +211,13 @@ def ssa_run(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: in
     arrs = [np.ascontiguousarray(v, np.int32) for v in (net.r0, net.r1, net.p0, net.p1)]
     rate = np.ascontiguousarray(net.rate, np.float32)
     if Q is None:
-        lib().orc_ssa_run(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), _p(idv), seed, step0,
-                          steps, t_max, _p(t), _p(times), _p(fired), threads)
+        lib().orc_ssa_run(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), period, _p(idv), seed,
+                          step0, steps, t_max, _p(t), _p(times), _p(fired), threads)
     else:
         q = np.ascontiguousarray(Q, dtype=np.uint32)
         lib().orc_ssa_run_proposal(_p(x), R, N, M, *[_p(v) for v in arrs], _p(rate), _p(q), M,
-                                   qfloor, _p(idv), seed, step0, steps, t_max, _p(t), _p(times),
-                                   _p(fired), threads)
+                                   qfloor, period, _p(idv), seed, step0, steps, t_max, _p(t),
+                                   _p(times), _p(fired), threads)
     return x, t, fired, times
 
 

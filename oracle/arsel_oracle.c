@@ -312,9 +312,12 @@ int orc_select_ragged(const float *alpha, const int64_t *offsets, int64_t n,
 /* -4: the proposal is unusable (sum Q >= 2^32, or Q_j = 0 where        */
 /* alpha_j > 0).                                                         */
 /* ------------------------------------------------------------------ */
+/* cbound (nullable): a bound C >= max_j alpha_j / Q_j used in place of the
+ * exact c (the bound-maintenance mode of the SSA run). */
 static int32_t select_proposal_one(const float *a, const uint32_t *q, int64_t M,
                                    uint32_t k, uint64_t seed, uint64_t step,
-                                   uint32_t t_max, uint32_t *trials, uint32_t *prefix)
+                                   uint32_t t_max, uint32_t *trials, uint32_t *prefix,
+                                   const double *cbound)
 {
     float amax;
     if (trials) *trials = 0;
@@ -332,6 +335,7 @@ static int32_t select_proposal_one(const float *a, const uint32_t *q, int64_t M,
         }
     }
     if (SQ >= ((uint64_t)1 << 32)) return -4;
+    if (cbound) c = *cbound;
     /* c+ >= alpha_j / Q_j for every j, so no acceptance probability saturates */
     double cplus = nextafter(c, INFINITY);
     uint32_t sq = (uint32_t)SQ;
@@ -386,7 +390,7 @@ int orc_select_proposal(const float *alpha, const uint32_t *Q, int64_t M, int64_
         for (int64_t k = 0; k < K; ++k) {
             index[k] = select_proposal_one(alpha + k * lda, Q + k * ldq, M, (uint32_t)k,
                                            seed, step, t_max,
-                                           trials ? trials + k : NULL, prefix);
+                                           trials ? trials + k : NULL, prefix, NULL);
         }
         free(prefix);
     }
@@ -462,46 +466,86 @@ int orc_ssa_chain(int32_t *X, int64_t R, int64_t N, int64_t M,
 /* ------------------------------------------------------------------ */
 /* Full SSA run (direct method, section "The Stochastic Simulation      */
 /* Algorithm"): each step recomputes every propensity from the state,   */
-/* selects the next reaction with the same uniform AR as the jump chain */
-/* (tag 2, instance id, step step0 + i), advances the time by           */
+/* selects the next reaction, advances the time by                      */
 /* tau = ln(1/u) / alpha_0 and applies the stoichiometry.  u comes from */
-/* Philox block 0xFFFFFFFE of the same stream, word 0, as               */
-/* (w + 1/2) 2^-32 in (0, 1); alpha_0 is the binary64 sum of the        */
-/* propensities in index order.  When every propensity is zero the      */
-/* state and time stay and the step records -1.                         */
+/* Philox block 0xFFFFFFFE of the tag-2 stream (instance id, step s),    */
+/* word 0, as (w + 1/2) 2^-32 in (0, 1); alpha_0 is the binary64 sum of  */
+/* the propensities in index order.  An invalid propensity records -2   */
+/* and every propensity zero records -1; state and time then stay.      */
+/*                                                                      */
+/* Selection: uniform AR on the tag-2 stream (the jump chain's) with    */
+/* the envelope B, or, with a proposal Q, proposal AR on the tag-1       */
+/* stream with Q'_j = max(Q_j, qfloor, 1) and the envelope C.  With      */
+/* period p, B and C are exact (alpha_max and max_j fl64(alpha_j/Q'_j))  */
+/* at the first step of the call and at steps s with s mod p = 0; at    */
+/* other steps they are the running maximum of those quantities since   */
+/* then (bounds kept from the propensities that change: the dependency  */
+/* graph idea the Introduction cites from the Next Reaction Method).    */
+/* Any B >= alpha_max and C >= max alpha_j / Q'_j leave the law of each  */
+/* step alpha_j / alpha_0; p = 1 (or 0) is exact at every step.          */
 /* ids[r] (or r when ids is NULL) is realization r's instance id.       */
 /* t[r] is read and advanced in place; times (nullable) receives t after */
 /* each step at [i * R + r]; fired (nullable) the selection at [i*R+r]. */
 /* ------------------------------------------------------------------ */
 #define TAU_BLOCK 0xFFFFFFFEu
 
-int orc_ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M,
-                const int32_t *r0, const int32_t *r1, const int32_t *p0, const int32_t *p1,
-                const float *rate, const uint32_t *ids, uint64_t seed, uint64_t step0,
-                int64_t steps, uint32_t t_max, double *t, double *times, int32_t *fired,
-                int threads)
+static int ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M, const int32_t *r0,
+                   const int32_t *r1, const int32_t *p0, const int32_t *p1, const float *rate,
+                   const uint32_t *Q, int64_t ldq, uint32_t qfloor, uint32_t period,
+                   const uint32_t *ids, uint64_t seed, uint64_t step0, int64_t steps,
+                   uint32_t t_max, double *t, double *times, int32_t *fired, int threads)
 {
+    if (period == 0) period = 1;
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #pragma omp parallel if (threads != 1)
 #endif
     {
         float *a = (float *)malloc(sizeof(float) * (size_t)M);
+        uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)M);
+        uint32_t *prefix = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)M);
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 1)
 #endif
         for (int64_t r = 0; r < R; ++r) {
             int32_t *x = X + r * N;
             const uint32_t id = ids ? ids[r] : (uint32_t)r;
+            if (Q) {
+                const uint32_t lo = qfloor > 0u ? qfloor : 1u;
+                for (int64_t j = 0; j < M; ++j) {
+                    const uint32_t v = Q[r * ldq + j];
+                    q[j] = v > lo ? v : lo;
+                }
+            }
+            float B = 0.0f;
+            double C = 0.0;
             for (int64_t i = 0; i < steps; ++i) {
                 const uint64_t s = step0 + (uint64_t)i;
+                const int exact = i == 0 || s % period == 0;
                 double a0 = 0.0;
                 for (int64_t j = 0; j < M; ++j) {
                     a[j] = mass_action(x, r0[j], r1[j], rate[j]);
                     a0 += (double)a[j];
                 }
-                int32_t j = select_uniform_one(a, 1, M, NULL, 0u, id, seed, s, 2u, t_max,
-                                               NULL, NULL);
+                float amax;
+                int32_t j;
+                if (scan_max(a, 1, M, &amax) != 0) {
+                    j = -2;
+                } else if (amax == 0.0f) {
+                    j = -1;
+                } else if (Q == NULL) {
+                    B = exact || amax > B ? amax : B;
+                    j = select_uniform_one(a, 1, M, &B, 0u, id, seed, s, 2u, t_max, NULL, NULL);
+                } else {
+                    double c = 0.0;
+                    for (int64_t jj = 0; jj < M; ++jj)
+                        if (a[jj] > 0.0f) {
+                            const double v = (double)a[jj] / (double)q[jj];
+                            if (v > c) c = v;
+                        }
+                    C = exact || c > C ? c : C;
+                    j = select_proposal_one(a, q, M, id, seed, s, t_max, NULL, prefix, &C);
+                }
                 if (fired) fired[i * R + r] = j;
                 if (j >= 0) {
                     uint32_t w[4];
@@ -517,8 +561,35 @@ int orc_ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M,
             }
         }
         free(a);
+        free(q);
+        free(prefix);
     }
     return 0;
+}
+
+int orc_ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M,
+                const int32_t *r0, const int32_t *r1, const int32_t *p0, const int32_t *p1,
+                const float *rate, uint32_t period, const uint32_t *ids, uint64_t seed,
+                uint64_t step0, int64_t steps, uint32_t t_max, double *t, double *times,
+                int32_t *fired, int threads)
+{
+    return ssa_run(X, R, N, M, r0, r1, p0, p1, rate, NULL, 0, 0u, period, ids, seed, step0,
+                   steps, t_max, t, times, fired, threads);
+}
+
+/* The run with an integer proposal (the learned proposal refreshed lazily,
+ * held fixed for the call; Q is [R][ldq] uint32, realization r's row).  The
+ * floor keeps reactions that turn active during the call covered, with a
+ * weight the caller sizes against the scale of Q. */
+int orc_ssa_run_proposal(int32_t *X, int64_t R, int64_t N, int64_t M,
+                         const int32_t *r0, const int32_t *r1, const int32_t *p0,
+                         const int32_t *p1, const float *rate, const uint32_t *Q, int64_t ldq,
+                         uint32_t qfloor, uint32_t period, const uint32_t *ids, uint64_t seed,
+                         uint64_t step0, int64_t steps, uint32_t t_max, double *t,
+                         double *times, int32_t *fired, int threads)
+{
+    return ssa_run(X, R, N, M, r0, r1, p0, p1, rate, Q, ldq, qfloor, period, ids, seed, step0,
+                   steps, t_max, t, times, fired, threads);
 }
 
 /* ------------------------------------------------------------------ */
@@ -588,66 +659,5 @@ int orc_select_ids(const float *alpha, int64_t M, int64_t n, const uint32_t *ids
     for (int64_t i = 0; i < n; ++i)
         index[i] = select_uniform_one(alpha + i * M, 1, M, NULL, 0u, ids[i], seed, step, 0u,
                                       t_max, alpha0 ? alpha0 + i : NULL, trials ? trials + i : NULL);
-    return 0;
-}
-
-/* Full SSA run with an integer proposal (the learned proposal refreshed
- * lazily, held fixed for the call): as orc_ssa_run, but each step selects
- * with proposal AR (tag 1, instance id, step s) on the current propensities
- * and Q'_j = max(Q_j, qfloor, 1) for every j, so reactions that become active
- * during the call stay covered, with a weight the caller sizes against the
- * scale of Q.  Q is [R][ldq] uint32 (realization r's row). */
-int orc_ssa_run_proposal(int32_t *X, int64_t R, int64_t N, int64_t M,
-                         const int32_t *r0, const int32_t *r1, const int32_t *p0,
-                         const int32_t *p1, const float *rate, const uint32_t *Q, int64_t ldq,
-                         uint32_t qfloor,
-                         const uint32_t *ids, uint64_t seed, uint64_t step0, int64_t steps,
-                         uint32_t t_max, double *t, double *times, int32_t *fired, int threads)
-{
-#ifdef _OPENMP
-    if (threads > 0) omp_set_num_threads(threads);
-#pragma omp parallel if (threads != 1)
-#endif
-    {
-        float *a = (float *)malloc(sizeof(float) * (size_t)M);
-        uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)M);
-        uint32_t *prefix = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)M);
-#ifdef _OPENMP
-#pragma omp for schedule(dynamic, 1)
-#endif
-        for (int64_t r = 0; r < R; ++r) {
-            int32_t *x = X + r * N;
-            const uint32_t id = ids ? ids[r] : (uint32_t)r;
-            const uint32_t lo = qfloor > 0u ? qfloor : 1u;
-            for (int64_t j = 0; j < M; ++j) {
-                const uint32_t v = Q[r * ldq + j];
-                q[j] = v > lo ? v : lo;
-            }
-            for (int64_t i = 0; i < steps; ++i) {
-                const uint64_t s = step0 + (uint64_t)i;
-                double a0 = 0.0;
-                for (int64_t j = 0; j < M; ++j) {
-                    a[j] = mass_action(x, r0[j], r1[j], rate[j]);
-                    a0 += (double)a[j];
-                }
-                int32_t j = select_proposal_one(a, q, M, id, seed, s, t_max, NULL, prefix);
-                if (fired) fired[i * R + r] = j;
-                if (j >= 0) {
-                    uint32_t w[4];
-                    draw(seed, TAU_BLOCK, id, s, 2u, w);
-                    const double u = ((double)w[0] + 0.5) * 0x1p-32;
-                    t[r] += log(1.0 / u) / a0;
-                    x[r0[j]] -= 1;
-                    if (r1[j] >= 0) x[r1[j]] -= 1;
-                    x[p0[j]] += 1;
-                    if (p1[j] >= 0) x[p1[j]] += 1;
-                }
-                if (times) times[i * R + r] = t[r];
-            }
-        }
-        free(a);
-        free(q);
-        free(prefix);
-    }
     return 0;
 }

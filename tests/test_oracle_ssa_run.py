@@ -3,6 +3,7 @@ tau = ln(1/u) / alpha_0, state update; section "The Stochastic Simulation
 Algorithm"): the state sequence is the jump chain's, the times follow the
 closed-form laws of the direct method, absorbed realizations stop."""
 import numpy as np
+import pytest
 from scipy import stats
 
 import oracle
@@ -100,3 +101,81 @@ def test_proposal_floor_is_a_plain_maximum():
     d = oracle.ssa_run(net, X0, seed=3, step0=0, steps=40, Q=np.full_like(Q, 400))[2]
     e = oracle.ssa_run(net, X0, seed=3, step0=0, steps=40, Q=Q + 400)[2]
     assert np.array_equal(c, d) and not np.array_equal(c, e)
+
+
+# ---- bound maintenance (period p): envelopes exact every p steps ----
+
+def _tiny_net():
+    """4 species, 6 reactions with small counts, so one firing moves the
+    propensities (and alpha_max) a lot."""
+    i32 = lambda v: np.array(v, np.int32)
+    return workloads.Network(N=4, r0=i32([0, 1, 2, 0, 3, 1]), r1=i32([-1, -1, 3, 1, -1, 1]),
+                             p0=i32([1, 2, 0, 2, 0, 3]), p1=i32([-1, -1, 1, 3, -1, 0]),
+                             rate=np.array([1.0, 0.5, 2.0, 0.7, 3.0, 0.25], np.float32))
+
+
+def _alpha(net, x):
+    """Mass-action propensities written out independently of the oracle."""
+    a = np.zeros(net.M)
+    for j in range(net.M):
+        u, v = int(net.r0[j]), int(net.r1[j])
+        h = x[u] if v < 0 else (x[u] * (x[u] - 1) // 2 if v == u else x[u] * x[v])
+        a[j] = float(net.rate[j]) * h
+    return a
+
+
+def _pair_law(net, x0):
+    a0 = _alpha(net, x0)
+    law = np.zeros((net.M, net.M))
+    for j in range(net.M):
+        if a0[j] == 0:
+            continue
+        x1 = x0.copy()
+        for sp, d in ((net.r0[j], -1), (net.r1[j], -1), (net.p0[j], 1), (net.p1[j], 1)):
+            if sp >= 0:
+                x1[sp] += d
+        a1 = _alpha(net, x1)
+        law[j] = a0[j] / a0.sum() * a1 / a1.sum()
+    return law.ravel()
+
+
+@pytest.mark.parametrize("proposal,t_max", [(False, 4096), (True, 4096), (False, 1), (True, 1)])
+def test_bound_mode_keeps_the_two_step_law(proposal, t_max):
+    """Step 2 of a call with a long period selects with the running-maximum
+    envelope (not the exact one); the joint law of the first two selections
+    from one state is still the product of alpha_j / alpha_0 at each state,
+    also when the trial budget forces the fallback."""
+    net = _tiny_net()
+    x0 = np.array([3, 2, 4, 2], np.int32)
+    R = 150000
+    X0 = np.tile(x0, (R, 1))
+    Q = None
+    if proposal:
+        Q = np.tile(np.array([[9, 1, 30, 2, 5, 40]], np.uint32), (R, 1))
+    _, _, f, _ = oracle.ssa_run(net, X0, seed=21, step0=1, steps=2, t_max=t_max, threads=8,
+                                Q=Q, period=1000)
+    assert np.all(f >= 0)
+    counts = np.bincount(f[0] * net.M + f[1], minlength=net.M * net.M)
+    assert laws.chi_square_p(counts, _pair_law(net, x0)) > 0.01
+    # the envelope really differs from the exact one at step 2 for some draws
+    _, _, fe, _ = oracle.ssa_run(net, X0[:4000], seed=21, step0=1, steps=2, t_max=t_max,
+                                 threads=8, Q=None if Q is None else Q[:4000], period=1)
+    assert np.array_equal(fe[0], f[0, :4000]) and not np.array_equal(fe[1], f[1, :4000])
+
+
+@pytest.mark.parametrize("proposal", [False, True])
+def test_bound_mode_resumes_at_period_boundaries(proposal):
+    """Envelopes are exact at s mod p = 0, so a run split there equals the
+    whole run; period 1 is the exact-every-step run."""
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    X0 = workloads.poisson_counts(N=64, R=12, seed=6)
+    Q = np.random.default_rng(3).integers(0, 500, size=(12, 100)).astype(np.uint32) if proposal else None
+    whole = oracle.ssa_run(net, X0, seed=4, step0=0, steps=96, threads=8, Q=Q, period=16)
+    x1, t1, f1, _ = oracle.ssa_run(net, X0, seed=4, step0=0, steps=48, threads=8, Q=Q, period=16)
+    x2, t2, f2, _ = oracle.ssa_run(net, x1, seed=4, step0=48, steps=48, t0=t1, threads=8, Q=Q,
+                                   period=16)
+    assert np.array_equal(whole[0], x2) and np.array_equal(whole[2], np.vstack([f1, f2]))
+    np.testing.assert_allclose(whole[1], t2, rtol=1e-14)
+    a = oracle.ssa_run(net, X0, seed=4, step0=0, steps=96, threads=8, Q=Q, period=1)
+    b = oracle.ssa_run(net, X0, seed=4, step0=0, steps=96, threads=8, Q=Q, period=0)
+    assert np.array_equal(a[2], b[2]) and not np.array_equal(a[2], whole[2])
