@@ -218,13 +218,18 @@ def bench_learned(torch, np, arsel, workloads, epochs: int = 8, lr0: float = 2e-
                 "acceptance_per_trial": {"uniform": round(float(np.mean(accs_u)), 5),
                                          "learned": round(float(np.mean(accs_l)), 5)},
                 "selections_per_s": {"uniform_AR": round(ru, 1), "learned": round(rl, 1),
-                                     "speedup": round(rl / ru, 2)}}}
+                                     "speedup": round(rl / ru, 2)}}}, lp
 
 
-def bench_ssa(torch, np, workloads):
+def bench_ssa(torch, np, arsel, workloads, lp=None, refresh: int = 1000, period: int = 64):
     """Full batched SSA on the N=641 / M=1029 mass-action network: R = 16384
     realizations x 10^4 steps, one launch (selection, time step,
-    stoichiometry, dependency-graph propensity updates per step)."""
+    stoichiometry, dependency-graph propensity updates per step), with the
+    envelopes exact at every step (period 1) and maintained from the changed
+    propensities (exact every `period` steps).  With a trained proposal
+    network lp, also the same runs selecting with its proposal, refreshed
+    every `refresh` steps (MLP forward on the current states, inside the
+    timed region)."""
     from paper_1404_0027_amd import learned
 
     net = workloads.mass_action_network()
@@ -234,15 +239,21 @@ def bench_ssa(torch, np, workloads):
     X = X0.clone()
     t = torch.zeros(R, dtype=torch.float64, device="cuda")
     dn.run(X, t, seed=SEED, step0=0, steps=100)            # warm-up (and the dependency graph)
-    X.copy_(X0)
-    t.zero_()
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    dn.run(X, t, seed=SEED, step0=0, steps=steps)
-    e1.record()
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) * 1e-3
+
+    def timed(fn):
+        X.copy_(X0)
+        t.zero_()
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3
+
+    sec = {p: timed(lambda: dn.run(X, t, seed=SEED, step0=0, steps=steps, period=p))
+           for p in (1, period)}
+    sim_t = float(t.mean().item())
     # the jump chain kernel (full propensity recompute each step) for reference
     X.copy_(X0)
     torch.cuda.synchronize()
@@ -251,13 +262,53 @@ def bench_ssa(torch, np, workloads):
     e1.record()
     torch.cuda.synchronize()
     sec_chain = e0.elapsed_time(e1) * 1e-3 * (steps / 1000)
-    return {"workload": "full SSA, mass-action network N=641, M=1029, counts Poisson(50): "
-                        f"R={R} realizations x {steps} steps in one launch",
-            "selections_per_s": round(R * steps / sec, 1), "seconds": round(sec, 4),
-            "mean_simulated_time": float(t.mean().item()),
-            "jump_chain_full_recompute_selections_per_s": round(R * steps / sec_chain, 1),
-            "note": "per step: exact alpha_max and alpha_0 over LDS-resident propensities, AR "
-                    "selection, tau, stoichiometry, propensities of the affected reactions"}
+    out = {"workload": "full SSA, mass-action network N=641, M=1029, counts Poisson(50): "
+                       f"R={R} realizations x {steps} steps in one launch",
+           "selections_per_s": round(R * steps / sec[period], 1),
+           "seconds": round(sec[period], 4), "period": period,
+           "exact_envelope_every_step": {"selections_per_s": round(R * steps / sec[1], 1),
+                                         "seconds": round(sec[1], 4)},
+           "mean_simulated_time": sim_t,
+           "jump_chain_full_recompute_selections_per_s": round(R * steps / sec_chain, 1),
+           "note": "per step: AR selection against the step's envelope, tau, stoichiometry, "
+                   "propensities of the affected reactions; envelopes and alpha_0 exact every "
+                   f"{period} steps (one pass over the LDS-resident propensities), kept from "
+                   "the changed propensities between"}
+    if lp is None:
+        return out
+
+    # the network's Q sums to about 2^(31 - ceil(log2 M)); reactions it left
+    # out (inactive at the refresh) weigh about 1/8 of an average one
+    qfloor = (1 << (31 - (net.M - 1).bit_length())) // (8 * net.M)
+
+    def learned_run(p, acc=None):
+        for seg in range(0, steps, refresh):
+            a = dn.propensities(X)
+            Q, _ = lp.forward(X, a)
+            if acc is not None:       # acceptance per trial on the refresh states
+                tr = torch.empty(R, dtype=torch.int32, device="cuda")
+                arsel.select(a, net.M, R, net.M, arsel.AOS, seed=SEED, step=seg, trials=tr)
+                acc["uniform"].append(_acceptance(np, tr))
+                arsel.select_proposal(a, Q, seed=SEED, step=seg, trials=tr)
+                acc["learned"].append(_acceptance(np, tr))
+            dn.run(X, t, seed=SEED, step0=seg, steps=min(refresh, steps - seg), Q=Q, qfloor=qfloor,
+                   period=p)
+
+    acc = {"uniform": [], "learned": []}
+    timed(lambda: learned_run(period, acc))                 # (acceptance pass)
+    sec_l = {p: timed(lambda: learned_run(p)) for p in (1, period)}
+    out["with_learned_proposal"] = {
+        "what": f"same runs, steps select with the trained network's proposal "
+                f"Q' = max(Q, {qfloor}), Q refreshed every {refresh} steps (MLP forward timed)",
+        "selections_per_s": round(R * steps / sec_l[period], 1),
+        "seconds": round(sec_l[period], 4),
+        "exact_envelope_every_step_selections_per_s": round(R * steps / sec_l[1], 1),
+        "speedup_vs_uniform": round(sec[period] / sec_l[period], 3),
+        "acceptance_per_trial_at_refresh": {
+            "uniform": round(float(np.mean(acc["uniform"])), 5),
+            "learned": round(float(np.mean(acc["learned"])), 5)},
+        "mean_simulated_time": float(t.mean().item())}
+    return out
 
 
 def bench_paper_table1(torch, np, arsel, workloads):
@@ -416,9 +467,10 @@ def main() -> int:
         print("[bench] uneven batch", file=sys.stderr, flush=True)
         ragged = bench_ragged(torch, arsel, workloads)
         print("[bench] learned proposal", file=sys.stderr, flush=True)
-        learned_res = bench_learned(torch, np, arsel, workloads)
+        learned_res, lp = bench_learned(torch, np, arsel, workloads)
         print("[bench] full SSA run", file=sys.stderr, flush=True)
-        ssa_res = bench_ssa(torch, np, workloads)
+        ssa_res = bench_ssa(torch, np, arsel, workloads, lp=lp)
+        del lp
         print("[bench] paper scheme vs exact AR (Table 1 style)", file=sys.stderr, flush=True)
         paper_res = bench_paper_table1(torch, np, arsel, workloads)
         print("[bench] 10^6 realizations in one launch", file=sys.stderr, flush=True)

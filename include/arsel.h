@@ -230,38 +230,54 @@ int arsel_ssa_deps(arsel_ctx *ctx, const arsel_network *net, int32_t *deps, int3
 
 /* Full SSA run, the direct method of section "The Stochastic Simulation
  * Algorithm" with the AR selection: for R realizations (X int32 [R][N] in
- * place, t double [R] in place, DEVICE) and steps i = 0 .. steps-1, each step
- * selects j exactly as arsel_ssa_chain does (uniform AR, tag-2 stream,
- * instance r, step step0 + i), advances t by ln(1/u) / alpha_0 with
- * u = (w + 1/2) 2^-32 from word 0 of Philox block 0xFFFFFFFE of the same
- * stream and alpha_0 the sum of the propensities in binary64, applies the
- * stoichiometry and recomputes the propensities of the reactions deps lists
- * for j.  A step where nothing can fire records -1 and leaves state and
- * time.  fired (nullable, [steps][R]) and times (nullable, [steps][R], t
- * after each step) are outputs.  States and selections are bit-identical to
- * the sequential definition; the times agree with it to rounding (the sum
- * order of alpha_0 and the log implementation differ). */
+ * place, t double [R] in place, DEVICE) and steps i = 0 .. steps-1 (step
+ * s = step0 + i), each step selects j with uniform AR on the tag-2 stream
+ * (instance r, step s: with period 1 exactly as arsel_ssa_chain), advances t
+ * by ln(1/u) / alpha_0 with u = (w + 1/2) 2^-32 from word 0 of Philox block
+ * 0xFFFFFFFE of the same stream, applies the stoichiometry and recomputes the
+ * propensities of the reactions deps lists for j.
+ *
+ * Bound maintenance: the envelope B of the acceptance test (and alpha_0) is
+ * exact at the call's first step and at steps with s mod period = 0; between
+ * them B is the running maximum of alpha_max since then, kept from the
+ * changed propensities, and alpha_0 is updated by their differences.  Any
+ * B >= alpha_max leaves the law alpha_j / alpha_0 of every step; the
+ * fallback uses the exact alpha_max.  period 0 or 1: exact at every step (one
+ * pass over the M propensities per step); a larger period makes a step read
+ * only its candidates and the changed reactions.  Results depend on where
+ * calls start, except when they start at multiples of period.
+ *
+ * An invalid propensity (NaN, negative, +inf) records -2 and no positive one
+ * -1; the state and time then stay.  fired (nullable, [steps][R]) and times
+ * (nullable, [steps][R], t after each step) are outputs.  States and
+ * selections are bit-identical to the sequential definition; the times agree
+ * with it to rounding (the sum order of alpha_0, its updates between exact
+ * steps and the log implementation differ). */
 int arsel_ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
                   const int32_t *ndeps, int32_t *X, int32_t R, uint64_t seed, uint64_t step0,
-                  int64_t steps, uint32_t t_max, double *t, double *times, int32_t *fired,
-                  void *stream);
+                  int64_t steps, uint32_t t_max, uint32_t period, double *t, double *times,
+                  int32_t *fired, void *stream);
 
 /* The full SSA run selecting with an integer proposal (the learned proposal of
  * the neural-network extension, refreshed lazily by the caller between
  * calls): as arsel_ssa_run, except that each step selects as
  * arsel_select_proposal does (tag-1 stream, instance r, step step0 + i) with
- * Q'_j = max(Q_j, 1), Q the DEVICE uint32 row [r][ldq] of realization r
- * (ldq >= M, held fixed for the call).  Q' is positive everywhere, so a
- * reaction that becomes active during the call stays covered and each step's
- * law is alpha_j / alpha_0; c = max_j fl64(alpha_j / Q'_j) is recomputed
- * exactly every step.  A realization with sum Q' >= 2^32 records -4 at every
- * step and does not move.  Q NULL: ARSEL_ERR_NULL; ldq < M: ARSEL_ERR_LD;
- * (N + 2 M) * 4 bytes above one workgroup's LDS: ARSEL_ERR_SIZE. */
+ * Q'_j = max(Q_j, qfloor, 1), Q the DEVICE uint32 row [r][ldq] of realization
+ * r (ldq >= M, held fixed for the call), and the envelope C >=
+ * max_j fl64(alpha_j / Q'_j), exact at the same steps as B and a running
+ * maximum between.  Q' is positive everywhere, so a reaction that becomes
+ * active during the call stays covered and each step's law is
+ * alpha_j / alpha_0.  qfloor sets the weight of reactions the proposal left
+ * out: about sum Q / (8 M) bounds the acceptance rate below by roughly 1/9 of
+ * uniform AR's, whatever turns active.  A realization with sum Q' >= 2^32
+ * records -4 at every step and does not move.  Q NULL: ARSEL_ERR_NULL;
+ * ldq < M: ARSEL_ERR_LD; (N + 2 M) * 4 bytes above one workgroup's LDS:
+ * ARSEL_ERR_SIZE. */
 int arsel_ssa_run_proposal(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
-                           const int32_t *ndeps, const uint32_t *Q, int64_t ldq, int32_t *X,
-                           int32_t R, uint64_t seed, uint64_t step0, int64_t steps,
-                           uint32_t t_max, double *t, double *times, int32_t *fired,
-                           void *stream);
+                           const int32_t *ndeps, const uint32_t *Q, int64_t ldq, uint32_t qfloor,
+                           int32_t *X, int32_t R, uint64_t seed, uint64_t step0, int64_t steps,
+                           uint32_t t_max, uint32_t period, double *t, double *times,
+                           int32_t *fired, void *stream);
 
 /* ------------------------------------------------------------------------
  * Learned proposal (BF16 MLP on MFMA, FP32 accumulation).

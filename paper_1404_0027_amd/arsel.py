@@ -106,10 +106,12 @@ _EXTRA_SIGNATURES = {
                            ctypes.c_uint64, ctypes.c_uint64, _P, _P],
     "arsel_ssa_deps": [_P, ctypes.POINTER(Network), _P, _P, _P],
     "arsel_ssa_run": [_P, ctypes.POINTER(Network), _P, _P, _P, ctypes.c_int32, ctypes.c_uint64,
-                      ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, _P, _P, _P, _P],
-    "arsel_ssa_run_proposal": [_P, ctypes.POINTER(Network), _P, _P, _P, ctypes.c_int64, _P,
-                               ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
-                               ctypes.c_uint32, _P, _P, _P, _P],
+                      ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, _P, _P,
+                      _P, _P],
+    "arsel_ssa_run_proposal": [_P, ctypes.POINTER(Network), _P, _P, _P, ctypes.c_int64,
+                               ctypes.c_uint32, _P, ctypes.c_int32, ctypes.c_uint64,
+                               ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32,
+                               _P, _P, _P, _P],
 }
 
 SSA_DEP_MAX = 64

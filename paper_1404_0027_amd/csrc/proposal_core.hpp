@@ -25,12 +25,39 @@ __device__ __forceinline__ double wave_max_f64(double x)
     return x;
 }
 
-// c = max over the support (alpha_j > 0) of fl64(alpha_j / Q_j), Q_j = qat(j);
-// miss: some alpha_j > 0 has Q_j = 0.  Rounding is monotone, so c is fl64 of
-// the largest exact ratio: a float estimate of each ratio (relative error
-// < 2^-22 while the largest is above 2^-100) keeps every index within 2^-19
-// of the largest estimate, which contains the argmax, and only those get the
-// binary64 division.  Tiny ratios take the exact loop over all indices.
+// Filter estimate of alpha_j / q for q >= 1: the conversion of q, the
+// hardware reciprocal (1 ulp) and the product keep its relative error below
+// 2^-21 whenever the result is normal.
+__device__ __forceinline__ float ratio_estimate(float x, uint32_t q)
+{
+    return x * __builtin_amdgcn_rcpf((float)q);
+}
+
+// c = max over the support (alpha_j > 0) of fl64(alpha_j / Q_j), Q_j = qat(j)
+// > 0 there, given rmax, the wavefront maximum of the estimates over the
+// support.  Rounding is monotone, so c is fl64 of the largest exact ratio;
+// while rmax >= 2^-100 every index whose ratio is within 2^-20 of the largest
+// has its estimate within 2^-19 of rmax, and only indices in that band get
+// the binary64 division.  Tiny ratios take the exact loop over all indices.
+template <class QAt>
+__device__ double wave_proposal_c_band(const float *sa, uint32_t M, QAt qat, float rmax)
+{
+    const int lane = lane_id();
+    const bool fast = rmax >= 0x1p-100f;
+    const float thr = rmax - rmax * 0x1p-19f;
+    double c = 0.0;
+    for (uint32_t j = lane; j < M; j += kWave) {
+        const float x = sa[j];
+        if (x > 0.0f) {
+            const uint32_t q = qat(j);
+            if (q != 0 && (!fast || ratio_estimate(x, q) >= thr))
+                c = fmax(c, (double)x / (double)q);
+        }
+    }
+    return wave_max_f64(c);
+}
+
+// The same c with its own estimate pass; miss: some alpha_j > 0 has Q_j = 0.
 template <class QAt>
 __device__ double wave_proposal_c(const float *sa, uint32_t M, QAt qat, bool &miss)
 {
@@ -44,26 +71,17 @@ __device__ double wave_proposal_c(const float *sa, uint32_t M, QAt qat, bool &mi
             if (q == 0)
                 ms = true;
             else
-                rmax = fmaxf(rmax, x / (float)q);
+                rmax = fmaxf(rmax, ratio_estimate(x, q));
         }
     }
     miss = __ballot(ms) != 0;
-    rmax = wave_max(rmax);
-    const bool fast = rmax >= 0x1p-100f;
-    const float thr = rmax - rmax * 0x1p-19f;
-    double c = 0.0;
-    for (uint32_t j = lane; j < M; j += kWave) {
-        const float x = sa[j];
-        const uint32_t q = qat(j);
-        if (x > 0.0f && q != 0 && (!fast || x / (float)q >= thr))
-            c = fmax(c, (double)x / (double)q);
-    }
-    return wave_max_f64(c);
+    return wave_proposal_c_band(sa, M, qat, wave_max(rmax));
 }
 
-// The rounds and the fallback for one instance: alpha in sa, inclusive prefix
-// of Q in sp (S = sum Q < 2^32, every Q_j > 0 on the support), c+ the
-// envelope, amax the exact maximum of alpha (> 0).
+// The rounds and the fallback for one instance: alpha in sa (valid, not all
+// zero), inclusive prefix of Q in sp (S = sum Q < 2^32, every Q_j > 0 on the
+// support), c+ the envelope (>= max_j alpha_j / Q_j), amax the exact maximum
+// of alpha, or any value <= 0 when unknown (the fallback then scans for it).
 __device__ inline Outcome wave_proposal_rounds(const float *sa, const uint32_t *sp, uint32_t M,
                                                uint32_t S, double cplus, float amax,
                                                const Stream &st, uint32_t t_max)
@@ -111,8 +129,12 @@ __device__ inline Outcome wave_proposal_rounds(const float *sa, const uint32_t *
         o.index = (int32_t)(uint32_t)key;
         o.trials = (uint32_t)(key >> 32) + 1;
     } else {
-        const int shift = 63 - ceil_log2_u32(M) - exponent_above(amax);
         const ContigAcc acc{sa};
+        if (!(amax > 0.0f)) {
+            bool bad;
+            wave_scan(acc, M, amax, bad);
+        }
+        const int shift = 63 - ceil_log2_u32(M) - exponent_above(amax);
         const uint64_t Sf = wave_fixed_sum(acc, M, shift);
         const Words w = st.block(kFallbackBlock);
         const uint64_t V = (uint64_t)w.w0 | ((uint64_t)w.w1 << 32);

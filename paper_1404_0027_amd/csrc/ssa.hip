@@ -149,21 +149,49 @@ struct RunArgs {
     int32_t *fired;      // [steps][R] or null
     const uint32_t *Q;   // [R][ldq] integer proposal (proposal run only)
     int64_t ldq;
+    uint32_t qfloor;     // Q'_j = max(Q_j, qfloor, 1)
+    uint32_t period;     // exact envelopes every period steps (0 or 1: every step)
 };
 
+// Valid propensity: non-negative (-0.0 included) and finite.
+__device__ __forceinline__ bool valid_prop(float v)
+{
+    return v >= 0.0f && v != __builtin_inff();
+}
+
+// Sum over the wavefront of two signed counts (|sum| < 2^31 each).
+__device__ __forceinline__ void wave_sum_pair(int32_t &a, int32_t &b)
+{
+    const uint64_t tot = wave_sum_u64((uint64_t)(int64_t)a + ((uint64_t)(int64_t)b << 32));
+    a = (int32_t)(uint32_t)tot;
+    b = (int32_t)(((int64_t)tot - (int64_t)a) >> 32);
+}
+
 // One wavefront per realization, counts and propensities in its LDS.  Each
-// step: exact alpha_max (bit maximum) and alpha_0 over the propensities, the
-// AR selection, tau = ln(1/u) / alpha_0 with u from Philox block 0xFFFFFFFE
-// of the tag-2 stream, the stoichiometry, and the propensities of the
-// reactions the fired one affects.  A step with nothing able to fire leaves
-// state and time.  PROP = false selects with uniform AR on the tag-2 stream
-// (the jump chain's); PROP = true with the integer proposal Q'_j =
-// max(Q_j, 1) of the realization (its inclusive prefix kept in LDS for the
-// whole call) on the tag-1 stream, with c = max_j fl64(alpha_j / Q'_j)
-// recomputed exactly every step, so every step's law is alpha_j / alpha_0.
+// step selects the next reaction with the envelope of the step, advances the
+// time by tau = ln(1/u) / alpha_0 (u from Philox block 0xFFFFFFFE of the
+// tag-2 stream), applies the stoichiometry and recomputes the propensities of
+// the reactions the fired one affects (the dependency graph).
+//
+// Bound maintenance with period p: at the call's first step and at steps
+// s with s mod p = 0 one pass over the propensities takes the exact
+// alpha_max (the envelope B), alpha_0, the numbers of positive and of invalid
+// propensities and, with a proposal, the exact c; between those steps the
+// update of the affected reactions keeps the counts, alpha_0 (incrementally,
+// to rounding) and the running maxima B and C, so a step reads only its
+// candidates and the changed reactions.  B >= alpha_max and C >= max_j
+// alpha_j / Q'_j keep each step's law alpha_j / alpha_0; the fallback still
+// uses the exact alpha_max.  p = 1 takes the pass at every step.
+//
+// PROP = false selects with uniform AR on the tag-2 stream (the jump
+// chain's); PROP = true with the integer proposal Q'_j = max(Q_j, qfloor, 1)
+// of the realization (its inclusive prefix kept in LDS for the whole call)
+// on the tag-1 stream.  An invalid propensity gives -2 and no positive one
+// -1 (both permanent: nothing fires), sum Q' >= 2^32 gives -4.
 template <int NW, bool PROP>
 __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
 {
+    static_assert(kDepMax == kWave, "one dependency row per wavefront load");
     extern __shared__ int32_t lds_i[];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
@@ -178,8 +206,9 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
     uint64_t sumq = 0;
     if (PROP) {
         const uint32_t *gq = c.Q + (int64_t)r * c.ldq;
+        const uint32_t lo = max(c.qfloor, 1u);
         for (int j = lane; j < M; j += kWave) {
-            const uint32_t q = max(gq[j], 1u);
+            const uint32_t q = max(gq[j], lo);
             sp[j] = q;
             sumq += q;
         }
@@ -189,67 +218,137 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
     if (PROP) wave_prefix_u32([&](uint32_t j) { return sp[j]; }, sp, (uint32_t)M);
     for (int j = lane; j < M; j += kWave) a[j] = mass_action(x, c.net.r0[j], c.net.r1[j], c.net.rate[j]);
     wave_sync_lds();
+    auto qat = [&](uint32_t jj) { return sp[jj] - (jj ? sp[jj - 1] : 0u); };
+    const uint64_t period = max(c.period, 1u);
+    const bool maintain = period > 1;   // with period 1 nothing is kept across steps
     double t = c.t[r];
+    double a0 = 0.0;     // alpha_0 (exact at refresh steps, updated between)
+    float B = 0.0f;      // envelope >= alpha_max (uniform)
+    double C = 0.0;      // envelope >= max_j alpha_j / Q'_j (proposal)
+    int32_t npos = 0, nbad = 0;
     for (int64_t i = 0; i < c.steps; ++i) {
         const uint64_t s = c.step0 + (uint64_t)i;
-        uint32_t mb = 0;
-        double a0 = 0.0;
-        for (int j = lane; j < M; j += kWave) {
-            const float v = a[j];
-            mb = max(mb, __float_as_uint(v));
-            a0 += (double)v;
-        }
-        mb = wave_max_u32(mb);
-        a0 = wave_sum_f64(a0);
-        const Stream st = make_stream(c.seed, s, (uint32_t)r, kTagSSA);
-        Outcome o;
-        if (PROP) {
-            float amax;
-            bool bad;
-            if (mb < 0x7F800000u) {
-                amax = __uint_as_float(mb);
-                bad = false;
+        const bool exact = i == 0 || s % period == 0;
+        if (exact) {
+            uint32_t mb = 0;
+            float rmax = 0.0f;
+            a0 = 0.0;
+            if (maintain) {
+                npos = 0;
+                nbad = 0;
+                for (int j = lane; j < M; j += kWave) {
+                    const float v = a[j];
+                    mb = max(mb, __float_as_uint(v) & 0x7FFFFFFFu);   // alpha_max while all are valid
+                    a0 += (double)v;
+                    npos += v > 0.0f;
+                    nbad += !valid_prop(v);
+                    if (PROP && v > 0.0f) rmax = fmaxf(rmax, ratio_estimate(v, qat((uint32_t)j)));
+                }
+                B = __uint_as_float(wave_max_u32(mb));
+                wave_sum_pair(npos, nbad);
             } else {
-                wave_scan(ContigAcc{a}, (uint32_t)M, amax, bad);
+                // the raw bit maximum certifies validity and is alpha_max below
+                // 0x7F800000; otherwise an exact scan decides
+                for (int j = lane; j < M; j += kWave) {
+                    const float v = a[j];
+                    mb = max(mb, __float_as_uint(v));
+                    a0 += (double)v;
+                    if (PROP && v > 0.0f) rmax = fmaxf(rmax, ratio_estimate(v, qat((uint32_t)j)));
+                }
+                mb = wave_max_u32(mb);
+                bool bad = false;
+                if (mb < 0x7F800000u)
+                    B = __uint_as_float(mb);
+                else
+                    wave_scan(ContigAcc{a}, (uint32_t)M, B, bad);
+                nbad = bad ? 1 : 0;
+                npos = B > 0.0f ? 1 : 0;
             }
-            if (bad)
-                o.index = -2;
-            else if (amax == 0.0f)
-                o.index = -1;
-            else if (sumq >= (1ull << 32))
+            a0 = wave_sum_f64(a0);
+            if (PROP && nbad == 0 && npos > 0 && sumq < (1ull << 32))
+                C = wave_proposal_c_band(a, (uint32_t)M, qat, wave_max(rmax));
+        }
+        Outcome o;
+        if (nbad != 0) {
+            o.index = -2;
+        } else if (npos == 0) {
+            o.index = -1;
+        } else if (PROP) {
+            if (sumq >= (1ull << 32)) {
                 o.index = -4;
-            else {
-                bool miss;   // never set: Q' >= 1 everywhere
-                const double cq = wave_proposal_c(
-                    a, (uint32_t)M, [&](uint32_t jj) { return sp[jj] - (jj ? sp[jj - 1] : 0u); }, miss);
-                const double cplus = __longlong_as_double(__double_as_longlong(cq) + 1);
+            } else {
+                const double cplus = __longlong_as_double(__double_as_longlong(C) + 1);
                 const Stream sq = make_stream(c.seed, s, (uint32_t)r, kTagProposal);
-                o = wave_proposal_rounds(a, sp, (uint32_t)M, (uint32_t)sumq, cplus, amax, sq, c.t_max);
+                o = wave_proposal_rounds(a, sp, (uint32_t)M, (uint32_t)sumq, cplus,
+                                         exact ? B : -1.0f, sq, c.t_max);
             }
         } else {
-            o = wave_select_hint(ContigAcc{a}, (uint32_t)M, mb, st, c.t_max, false);
+            ScanState ss;
+            ss.decided = false;
+            ss.scanned = exact;      // otherwise the fallback takes the exact maximum
+            ss.amax = B;
+            ss.env = B;
+            ss.o.alpha0 = 0.0f;
+            ss.o.trials = 0;
+            ss.o.index = -1;
+            o = wave_run(ContigAcc{a}, (uint32_t)M, ss, make_stream(c.seed, s, (uint32_t)r, kTagSSA),
+                         c.t_max);
         }
         const int32_t j = (int32_t)uniform_u32((uint32_t)o.index);
         if (c.fired && lane == 0) c.fired[i * c.R + r] = j;
         if (j >= 0) {
-            const Words w = st.block(kTauBlock);
+            // reaction j's stoichiometry, dependency count and whole dependency
+            // row (in bounds: the table is [M][kDepMax]) issued together
+            const int32_t nd = c.ndeps[j];
+            const int32_t dl = c.deps[(int64_t)j * kDepMax + lane];
+            const int32_t jr0 = c.net.r0[j], jr1 = c.net.r1[j], jp0 = c.net.p0[j], jp1 = c.net.p1[j];
+            const Words w = make_stream(c.seed, s, (uint32_t)r, kTagSSA).block(kTauBlock);
             const double u = ((double)w.w0 + 0.5) * 0x1p-32;
             t += log(1.0 / u) / a0;
             if (lane == 0) {
-                x[c.net.r0[j]] -= 1;
-                if (c.net.r1[j] >= 0) x[c.net.r1[j]] -= 1;
-                x[c.net.p0[j]] += 1;
-                if (c.net.p1[j] >= 0) x[c.net.p1[j]] += 1;
+                x[jr0] -= 1;
+                if (jr1 >= 0) x[jr1] -= 1;
+                x[jp0] += 1;
+                if (jp1 >= 0) x[jp1] += 1;
             }
             wave_sync_lds();
-            const int nd = (int)uniform_u32((uint32_t)c.ndeps[j]);
-            if (nd < 0) {
-                for (int jj = lane; jj < M; jj += kWave)
-                    a[jj] = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+            int32_t dpos = 0, dbad = 0;
+            double da0 = 0.0, cm = 0.0;
+            uint32_t bm = 0;
+            auto update = [&](int jj) {
+                const float old = a[jj];
+                const float nv = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+                a[jj] = nv;
+                dpos += (int32_t)(nv > 0.0f) - (int32_t)(old > 0.0f);
+                dbad += (int32_t)!valid_prop(nv) - (int32_t)!valid_prop(old);
+                da0 += (double)nv - (double)old;
+                if (valid_prop(nv)) {
+                    if (!PROP) bm = max(bm, __float_as_uint(nv) & 0x7FFFFFFFu);
+                    if (PROP && nv > 0.0f) cm = fmax(cm, (double)nv / (double)qat((uint32_t)jj));
+                }
+            };
+            if (maintain) {
+                if (nd < 0) {
+                    for (int jj = lane; jj < M; jj += kWave) update(jj);
+                } else if (lane < nd) {
+                    update(dl);
+                }
+                wave_sum_pair(dpos, dbad);
+                npos += dpos;
+                nbad += dbad;
+                a0 += wave_sum_f64(da0);
+                if (PROP)
+                    C = fmax(C, wave_max_f64(cm));
+                else
+                    B = fmaxf(B, __uint_as_float(wave_max_u32(bm)));
             } else {
-                for (int l = lane; l < nd; l += kWave) {
-                    const int jj = c.deps[(int64_t)j * kDepMax + l];
+                auto set = [&](int jj) {
                     a[jj] = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+                };
+                if (nd < 0) {
+                    for (int jj = lane; jj < M; jj += kWave) set(jj);
+                } else if (lane < nd) {
+                    set(dl);
                 }
             }
             wave_sync_lds();
@@ -330,9 +429,10 @@ extern "C" int arsel_ssa_deps(arsel_ctx *ctx, const arsel_network *net, int32_t 
 namespace arsel {
 
 static int ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
-                   const int32_t *ndeps, const uint32_t *Q, int64_t ldq, int32_t *X, int32_t R,
-                   uint64_t seed, uint64_t step0, int64_t steps, uint32_t t_max, double *t,
-                   double *times, int32_t *fired, void *stream)
+                   const int32_t *ndeps, const uint32_t *Q, int64_t ldq, uint32_t qfloor,
+                   int32_t *X, int32_t R, uint64_t seed, uint64_t step0, int64_t steps,
+                   uint32_t t_max, uint32_t period, double *t, double *times, int32_t *fired,
+                   void *stream)
 {
     if (!ctx) return ARSEL_ERR_NULL;
     int rc = check_net(net);
@@ -345,7 +445,7 @@ static int ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps
     if ((rc = ctx_activate(ctx))) return rc;
     const size_t per_wave = (size_t)(net->N + (prop ? 2 : 1) * (size_t)net->M) * 4;
     if (per_wave > ctx->lds_per_block) return ARSEL_ERR_SIZE;
-    RunArgs c{net_args(net), deps, ndeps, X, R, seed, step0, steps, t_max, t, times, fired, Q, ldq};
+    RunArgs c{net_args(net), deps, ndeps, X, R, seed, step0, steps, t_max, t, times, fired, Q, ldq, qfloor, period};
     hipStream_t s = (hipStream_t)stream;
     const bool four = per_wave * 4 <= ctx->tile_lds_bytes;
     const dim3 grid(four ? (R + 3) / 4 : R), block(four ? 256 : 64);
@@ -368,20 +468,21 @@ static int ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps
 
 extern "C" int arsel_ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
                              const int32_t *ndeps, int32_t *X, int32_t R, uint64_t seed,
-                             uint64_t step0, int64_t steps, uint32_t t_max, double *t,
-                             double *times, int32_t *fired, void *stream)
+                             uint64_t step0, int64_t steps, uint32_t t_max, uint32_t period,
+                             double *t, double *times, int32_t *fired, void *stream)
 {
-    return arsel::ssa_run(ctx, net, deps, ndeps, nullptr, 0, X, R, seed, step0, steps, t_max, t,
-                          times, fired, stream);
+    return arsel::ssa_run(ctx, net, deps, ndeps, nullptr, 0, 0, X, R, seed, step0, steps, t_max,
+                          period, t, times, fired, stream);
 }
 
 extern "C" int arsel_ssa_run_proposal(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
                                       const int32_t *ndeps, const uint32_t *Q, int64_t ldq,
-                                      int32_t *X, int32_t R, uint64_t seed, uint64_t step0,
-                                      int64_t steps, uint32_t t_max, double *t, double *times,
-                                      int32_t *fired, void *stream)
+                                      uint32_t qfloor, int32_t *X, int32_t R, uint64_t seed,
+                                      uint64_t step0, int64_t steps, uint32_t t_max,
+                                      uint32_t period, double *t, double *times, int32_t *fired,
+                                      void *stream)
 {
     if (!Q) return ARSEL_ERR_NULL;
-    return arsel::ssa_run(ctx, net, deps, ndeps, Q, ldq, X, R, seed, step0, steps, t_max, t,
-                          times, fired, stream);
+    return arsel::ssa_run(ctx, net, deps, ndeps, Q, ldq, qfloor, X, R, seed, step0, steps, t_max,
+                          period, t, times, fired, stream);
 }

@@ -73,10 +73,13 @@ class DeviceNetwork:
         return self._deps
 
     def run(self, X: torch.Tensor, t: torch.Tensor, *, seed: int, step0: int, steps: int,
-            t_max: int = 4096, want_fired: bool = False, want_times: bool = False, Q=None):
+            t_max: int = 4096, want_fired: bool = False, want_times: bool = False, Q=None,
+            qfloor: int = 1, period: int = 1):
         """Full SSA run in place on X [R, N] (int32) and t [R] (float64);
         with Q ([R, ldq] int32/uint32 proposal, ldq >= M) the steps select
-        with the proposal Q' = max(Q, 1).  Returns (fired [steps, R] or None,
+        with the proposal Q' = max(Q, qfloor, 1).  period: envelopes exact at
+        the first step and at steps s with s mod period = 0, maintained from
+        the changed propensities between.  Returns (fired [steps, R] or None,
         times [steps, R] or None)."""
         R = X.shape[0]
         arsel._need(X, torch.int32, R * self.N, "X", self.device)
@@ -84,8 +87,8 @@ class DeviceNetwork:
         d, n = self.deps()
         fired = torch.empty(steps, R, dtype=torch.int32, device=self.device) if want_fired else None
         times = torch.empty(steps, R, dtype=torch.float64, device=self.device) if want_times else None
-        common = (_ptr(X), R, seed & (2**64 - 1), step0 & (2**64 - 1), steps, t_max, _ptr(t),
-                  _ptr(times), _ptr(fired), _stream(self.device))
+        common = (_ptr(X), R, seed & (2**64 - 1), step0 & (2**64 - 1), steps, t_max, period,
+                  _ptr(t), _ptr(times), _ptr(fired), _stream(self.device))
         if Q is None:
             rc = lib().arsel_ssa_run(context(self.device), ctypes.byref(self.c), _ptr(d), _ptr(n),
                                      *common)
@@ -97,7 +100,7 @@ class DeviceNetwork:
                 raise arsel.ArselError("Q must be int32 or uint32")
             arsel._need(Q, Q.dtype, Q.numel(), "Q", self.device)
             rc = lib().arsel_ssa_run_proposal(context(self.device), ctypes.byref(self.c), _ptr(d),
-                                              _ptr(n), _ptr(Q), Q.shape[1], *common)
+                                              _ptr(n), _ptr(Q), Q.shape[1], qfloor, *common)
             _check(rc, "arsel_ssa_run_proposal")
         return fired, times
 

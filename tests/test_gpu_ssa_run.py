@@ -32,27 +32,34 @@ def test_dependency_graph(gpu):
             assert n[j] == len(want[j]) and list(d[j, :n[j]]) == want[j], j
 
 
-def _run_both(net, X0, *, seed, step0, steps, want_times=True):
+def _rtol(period):
+    # alpha_0 is exact at every step with period 1, updated by differences
+    # (to rounding, relative drift ~1e-16 per update) between exact steps
+    return 1e-12 if period <= 1 else 1e-10
+
+
+def _run_both(net, X0, *, seed, step0, steps, want_times=True, period=1, t_max=4096):
     dn = learned.DeviceNetwork(net)
     X = torch.from_numpy(X0).cuda()
     t = torch.zeros(X0.shape[0], dtype=torch.float64, device="cuda")
     fired, times = dn.run(X, t, seed=seed, step0=step0, steps=steps, want_fired=True,
-                          want_times=want_times)
+                          want_times=want_times, period=period, t_max=t_max)
     xo, to, fo, tmo = oracle.ssa_run(net, X0, seed=seed, step0=step0, steps=steps,
-                                     want_times=want_times, threads=8)
+                                     want_times=want_times, threads=8, period=period, t_max=t_max)
     assert np.array_equal(fired.cpu().numpy(), fo)
     assert np.array_equal(X.cpu().numpy(), xo)
-    np.testing.assert_allclose(t.cpu().numpy(), to, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(t.cpu().numpy(), to, rtol=_rtol(period), atol=0)
     if want_times:
-        np.testing.assert_allclose(times.cpu().numpy(), tmo, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(times.cpu().numpy(), tmo, rtol=_rtol(period), atol=0)
     return X, t
 
 
+@pytest.mark.parametrize("period", [1, 7, 64])
 @pytest.mark.parametrize("N,M,R,steps", [(64, 100, 40, 300), (641, 1029, 64, 200)])
-def test_run_matches_oracle(gpu, N, M, R, steps):
+def test_run_matches_oracle(gpu, N, M, R, steps, period):
     net = workloads.mass_action_network(N=N, M=M, seed=4)
     X0 = workloads.poisson_counts(N=N, R=R, seed=5)
-    _run_both(net, X0, seed=3, step0=11, steps=steps)
+    _run_both(net, X0, seed=3, step0=11, steps=steps, period=period)
 
 
 def test_run_absorbs_and_overflowing_dependency_lists(gpu):
@@ -62,6 +69,7 @@ def test_run_absorbs_and_overflowing_dependency_lists(gpu):
                             rate=np.array([0.5], np.float32))
     X0 = np.tile(np.array([[5, 0]], np.int32), (100, 1))
     _run_both(dec, X0, seed=1, step0=0, steps=9)
+    _run_both(dec, X0, seed=1, step0=0, steps=9, period=1000)
     # every reaction consumes species 0: dependency lists overflow (full recompute)
     rng = np.random.default_rng(3)
     M = 150
@@ -75,6 +83,7 @@ def test_run_absorbs_and_overflowing_dependency_lists(gpu):
     assert (n.cpu().numpy() == -1).any()
     X0 = rng.integers(20, 60, size=(30, 4)).astype(np.int32)
     _run_both(hub, X0, seed=2, step0=5, steps=200)
+    _run_both(hub, X0, seed=2, step0=5, steps=200, period=32)
 
 
 def test_run_resumes_in_segments(gpu):
@@ -92,7 +101,23 @@ def test_run_resumes_in_segments(gpu):
     np.testing.assert_allclose(ta.cpu().numpy(), tb.cpu().numpy(), rtol=1e-13)
 
 
-def test_run_full_size_sampled(gpu):
+def test_run_resumes_at_period_boundaries(gpu):
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    X0 = workloads.poisson_counts(N=64, R=32, seed=6)
+    dn = learned.DeviceNetwork(net)
+    Xa = torch.from_numpy(X0).cuda()
+    ta = torch.zeros(32, dtype=torch.float64, device="cuda")
+    fa, _ = dn.run(Xa, ta, seed=4, step0=0, steps=256, period=64, want_fired=True)
+    Xb = torch.from_numpy(X0).cuda()
+    tb = torch.zeros(32, dtype=torch.float64, device="cuda")
+    f1, _ = dn.run(Xb, tb, seed=4, step0=0, steps=128, period=64, want_fired=True)
+    f2, _ = dn.run(Xb, tb, seed=4, step0=128, steps=128, period=64, want_fired=True)
+    assert torch.equal(Xa, Xb) and torch.equal(fa, torch.cat([f1, f2]))
+    np.testing.assert_allclose(ta.cpu().numpy(), tb.cpu().numpy(), rtol=1e-10)
+
+
+@pytest.mark.parametrize("period", [1, 64])
+def test_run_full_size_sampled(gpu, period):
     """R = 16384 realizations x 10^4 steps of the N=641, M=1029 network in one
     launch; four realizations replayed by the oracle (instance ids kept)."""
     net = workloads.mass_action_network()
@@ -101,10 +126,11 @@ def test_run_full_size_sampled(gpu):
     dn = learned.DeviceNetwork(net)
     X = torch.from_numpy(X0).cuda()
     t = torch.zeros(R, dtype=torch.float64, device="cuda")
-    dn.run(X, t, seed=7, step0=0, steps=steps)
+    dn.run(X, t, seed=7, step0=0, steps=steps, period=period)
     torch.cuda.synchronize()
     ids = np.array([0, 5001, 12345, R - 1], np.uint32)
-    xo, to, _, _ = oracle.ssa_run(net, X0[ids], seed=7, step0=0, steps=steps, ids=ids, threads=4)
+    xo, to, _, _ = oracle.ssa_run(net, X0[ids], seed=7, step0=0, steps=steps, ids=ids, threads=4,
+                                  period=period)
     assert np.array_equal(X.cpu().numpy()[ids], xo)
     np.testing.assert_allclose(t.cpu().numpy()[ids], to, rtol=1e-9, atol=0)
     assert np.array_equal(X.cpu().numpy().sum(axis=1), X0.sum(axis=1))
@@ -121,7 +147,8 @@ def _shaped_q(net, X0):
     return np.floor(a / np.where(amax > 0, amax, 1.0) * 65535.0).astype(np.uint32)
 
 
-def _run_both_q(net, X0, Q, *, seed, step0, steps, t_max=4096, ldq=None, want_times=True):
+def _run_both_q(net, X0, Q, *, seed, step0, steps, t_max=4096, ldq=None, want_times=True,
+                qfloor=1, period=1):
     R, M = Q.shape
     ldq = ldq or M
     Qp = np.zeros((R, ldq), np.uint32)
@@ -132,20 +159,23 @@ def _run_both_q(net, X0, Q, *, seed, step0, steps, t_max=4096, ldq=None, want_ti
     t = torch.zeros(R, dtype=torch.float64, device="cuda")
     Qd = torch.from_numpy(Qp.view(np.int32)).cuda()
     fired, times = dn.run(X, t, seed=seed, step0=step0, steps=steps, t_max=t_max, want_fired=True,
-                          want_times=want_times, Q=Qd)
+                          want_times=want_times, Q=Qd, qfloor=qfloor, period=period)
     xo, to, fo, tmo = oracle.ssa_run(net, X0, seed=seed, step0=step0, steps=steps, t_max=t_max,
-                                     want_times=want_times, threads=8, Q=Q)
+                                     want_times=want_times, threads=8, Q=Q, qfloor=qfloor,
+                                     period=period)
     assert np.array_equal(fired.cpu().numpy(), fo)
     assert np.array_equal(X.cpu().numpy(), xo)
-    np.testing.assert_allclose(t.cpu().numpy(), to, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(t.cpu().numpy(), to, rtol=_rtol(period), atol=0)
     if want_times:
-        np.testing.assert_allclose(times.cpu().numpy(), tmo, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(times.cpu().numpy(), tmo, rtol=_rtol(period), atol=0)
     return fo
 
 
-@pytest.mark.parametrize("kind", ["random", "shaped"])
+@pytest.mark.parametrize("period", [1, 16])
+@pytest.mark.parametrize("kind,qfloor", [("random", 1), ("shaped", 1), ("shaped", 80),
+                                         ("random", 0xFFFFFFFF // 1000)])
 @pytest.mark.parametrize("N,M,R,steps", [(64, 100, 40, 300), (641, 1029, 64, 200)])
-def test_run_with_proposal_matches_oracle(gpu, N, M, R, steps, kind):
+def test_run_with_proposal_matches_oracle(gpu, N, M, R, steps, kind, qfloor, period):
     net = workloads.mass_action_network(N=N, M=M, seed=4)
     X0 = workloads.poisson_counts(N=N, R=R, seed=5)
     if kind == "random":
@@ -154,7 +184,9 @@ def test_run_with_proposal_matches_oracle(gpu, N, M, R, steps, kind):
         Q[rng.random((R, M)) < 0.2] = 0
     else:
         Q = _shaped_q(net, X0)
-    _run_both_q(net, X0, Q, seed=3, step0=11, steps=steps)
+    fo = _run_both_q(net, X0, Q, seed=3, step0=11, steps=steps, qfloor=qfloor, period=period)
+    # a floor with sum Q' >= 2^32 (the last case at M = 1029) stops every realization
+    assert np.all(fo == -4) == (qfloor * M >= 2**32)
 
 
 @pytest.mark.parametrize("t_max", [0, 1, 3])
@@ -164,6 +196,9 @@ def test_run_with_proposal_budgets_and_padding(gpu, t_max):
     X0 = workloads.poisson_counts(N=64, R=48, seed=7)
     Q = _shaped_q(net, X0)
     _run_both_q(net, X0, Q, seed=5, step0=2, steps=120, t_max=t_max, ldq=107)
+    _run_both_q(net, X0, Q, seed=5, step0=2, steps=120, t_max=t_max, ldq=107, period=50)
+    if t_max <= 1:    # the uniform run's fallback with maintained bounds too
+        _run_both(net, X0, seed=5, step0=2, steps=120, period=50, t_max=t_max)
 
 
 def test_run_with_proposal_overflow_and_absorption(gpu):
@@ -192,8 +227,8 @@ def test_run_with_proposal_argument_errors(gpu):
     t = torch.zeros(4, dtype=torch.float64, device="cuda")
     Q = torch.ones(4, 100, dtype=torch.int32, device="cuda")
     call = lambda q, ldq: arsel.lib().arsel_ssa_run_proposal(
-        arsel.context(0), ctypes.byref(dn.c), d.data_ptr(), n.data_ptr(), q, ldq, X.data_ptr(), 4,
-        1, 0, 5, 4096, t.data_ptr(), None, None, torch.cuda.current_stream().cuda_stream)
+        arsel.context(0), ctypes.byref(dn.c), d.data_ptr(), n.data_ptr(), q, ldq, 1, X.data_ptr(), 4,
+        1, 0, 5, 4096, 1, t.data_ptr(), None, None, torch.cuda.current_stream().cuda_stream)
     assert call(None, 100) == -1                  # Q NULL
     assert call(Q.data_ptr(), 99) == -4           # ldq < M
     assert call(Q.data_ptr(), 100) == 0
@@ -214,10 +249,11 @@ def test_run_with_proposal_full_size_sampled(gpu):
     dn = learned.DeviceNetwork(net)
     X = torch.from_numpy(X0).cuda()
     t = torch.zeros(R, dtype=torch.float64, device="cuda")
-    dn.run(X, t, seed=7, step0=0, steps=steps, Q=torch.from_numpy(Q.view(np.int32)).cuda())
+    dn.run(X, t, seed=7, step0=0, steps=steps, Q=torch.from_numpy(Q.view(np.int32)).cuda(),
+           qfloor=60, period=64)
     torch.cuda.synchronize()
     xo, to, _, _ = oracle.ssa_run(net, X0[ids], seed=7, step0=0, steps=steps, ids=ids, threads=4,
-                                  Q=Q[ids])
+                                  Q=Q[ids], qfloor=60, period=64)
     assert np.array_equal(X.cpu().numpy()[ids], xo)
     np.testing.assert_allclose(t.cpu().numpy()[ids], to, rtol=1e-9, atol=0)
     assert np.array_equal(X.cpu().numpy().sum(axis=1), X0.sum(axis=1))
