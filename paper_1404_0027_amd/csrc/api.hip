@@ -1,4 +1,5 @@
 // Context management and error strings of the C ABI.
+#include <math.h>
 #include <new>
 #include <string.h>
 
@@ -40,7 +41,19 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     c->staging_event = nullptr;
     c->ws = nullptr;
     c->ws_bytes = 0;
-    if (hipMalloc((void **)&c->queue, 256) != hipSuccess) {
+    c->ssa_tab = nullptr;
+    c->ssa_tab_bytes = 0;
+    c->ln_tab = nullptr;
+    double tab[2 * (kLnTabHi - kLnTabLo + 1)];
+    for (int i = kLnTabLo; i <= kLnTabHi; ++i) {
+        tab[2 * (i - kLnTabLo)] = log((double)i / 128.0);
+        tab[2 * (i - kLnTabLo) + 1] = 128.0 / (double)i;
+    }
+    if (hipMalloc((void **)&c->queue, 256) != hipSuccess ||
+        hipMalloc((void **)&c->ln_tab, sizeof(tab)) != hipSuccess ||
+        hipMemcpy(c->ln_tab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess) {
+        if (c->queue) (void)hipFree(c->queue);
+        if (c->ln_tab) (void)hipFree(c->ln_tab);
         delete c;
         (void)hipSetDevice(prev);
         return ARSEL_ERR_ALLOC;
@@ -64,6 +77,8 @@ extern "C" int arsel_destroy(arsel_ctx *ctx)
     }
     if (ctx->staging) (void)hipHostFree(ctx->staging);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->ssa_tab) (void)hipFree(ctx->ssa_tab);
+    if (ctx->ln_tab) (void)hipFree(ctx->ln_tab);
     (void)hipSetDevice(prev);
     delete ctx;
     return ARSEL_OK;

@@ -25,7 +25,13 @@ struct arsel_ctx {
     hipEvent_t staging_event; // completion of the last staging copy
     void *ws;                 // MLP workspace (activations, gradients), grown on demand
     size_t ws_bytes;
+    void *ssa_tab;            // packed dependency rows of the SSA run, grown on demand
+    size_t ssa_tab_bytes;
+    double *ln_tab;           // {ln(i/128), 128/i} for i = 96..192 (the run's logarithm)
 };
+
+// Grid of the run's table-driven logarithm: c_i = i / 128, i in [96, 192].
+constexpr int kLnTabLo = 96, kLnTabHi = 192;
 
 namespace arsel {
 

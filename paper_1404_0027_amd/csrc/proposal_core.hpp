@@ -11,19 +11,9 @@
 #pragma once
 
 #include "select_core.hpp"
+#include "wave_reduce.hpp"
 
 namespace arsel {
-
-__device__ __forceinline__ double wave_max_f64(double x)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint64_t b = (uint64_t)__double_as_longlong(x);
-        const uint64_t o = shfl_xor_u64(b, off);
-        x = fmax(x, __longlong_as_double((long long)o));
-    }
-    return x;
-}
 
 // Filter estimate of alpha_j / q for q >= 1: the conversion of q, the
 // hardware reciprocal (1 ulp) and the product keep its relative error below
@@ -54,7 +44,7 @@ __device__ double wave_proposal_c_band(const float *sa, uint32_t M, QAt qat, flo
                 c = fmax(c, (double)x / (double)q);
         }
     }
-    return wave_max_f64(c);
+    return wave_max_f64_nonneg(c);
 }
 
 // The same c with its own estimate pass; miss: some alpha_j > 0 has Q_j = 0.
@@ -75,7 +65,7 @@ __device__ double wave_proposal_c(const float *sa, uint32_t M, QAt qat, bool &mi
         }
     }
     miss = __ballot(ms) != 0;
-    return wave_proposal_c_band(sa, M, qat, wave_max(rmax));
+    return wave_proposal_c_band(sa, M, qat, wave_max_f32_nonneg(rmax));
 }
 
 // The rounds and the fallback for one instance: alpha in sa (valid, not all

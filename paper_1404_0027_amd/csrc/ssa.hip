@@ -25,8 +25,11 @@ __device__ __forceinline__ float mass_action(const int32_t *x, int32_t a, int32_
         h = (int64_t)x[a] * (x[a] - 1) / 2;
     else
         h = (int64_t)x[a] * x[b];
-    // nearest-even conversion of a non-negative count (h >= 0 for counts >= 0)
-    const float fh = h <= 0 ? 0.0f : fixed_to_float((uint64_t)h, 0);
+    // nearest-even conversion of a non-negative count (h >= 0 for counts >= 0):
+    // the hardware conversion below 2^32, the exact 64-bit one above
+    const float fh = h <= 0 ? 0.0f
+                     : h < (1ll << 32) ? (float)(uint32_t)h
+                                       : fixed_to_float((uint64_t)h, 0);
     return rate * fh;
 }
 
@@ -126,15 +129,40 @@ __global__ void k_ssa_deps(NetArgs n, int32_t *deps, int32_t *ndeps)
     ndeps[j] = cnt <= kDepMax ? cnt : -1;
 }
 
-__device__ __forceinline__ double wave_sum_f64(double x)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        x += __longlong_as_double((long long)shfl_xor_u64((uint64_t)__double_as_longlong(x), off));
-    return x;
-}
-
 constexpr uint32_t kTauBlock = 0xFFFFFFFEu;
+
+// -ln(u) for u = (w + 1/2) 2^-32, table-driven (P. T. P. Tang, "Table-driven
+// implementation of the logarithm function in IEEE floating-point
+// arithmetic", ACM TOMS 16, 1990): u = v 2^-33 with v = 2w + 1 exact, written
+// as m 2^e with m in [0.75, 1.5); c = i / 128 is the grid point nearest m
+// (so m - c is exact and r = (m - c) / c has |r| <= 2^-8 / 0.75), and
+// ln u = e ln 2 + ln c + log1p(r) with log1p by its Taylor series to degree 7
+// (the first omitted term is below 2^-56 relative).  Near u = 1, e = 0 and
+// c = 1 (ln c = 0), so the result keeps its relative accuracy there.  tab
+// holds {ln c_i, 1 / c_i} for i = 96 .. 192.
+__device__ __forceinline__ double neg_ln_u(uint32_t w, const double *tab)
+{
+    const uint64_t v = 2ull * w + 1ull;
+    const int n = 64 - __clzll((long long)v);             // 2^(n-1) <= v < 2^n
+    double m = ldexp((double)v, 1 - n);                    // [1, 2)
+    int e = n - 34;
+    if (m >= 1.5) {
+        m *= 0.5;
+        e += 1;
+    }
+    const int i = (int)rint(m * 128.0);
+    const double lnc = tab[2 * (i - kLnTabLo)], inv = tab[2 * (i - kLnTabLo) + 1];
+    const double r = (m - (double)i * 0x1p-7) * inv;
+    double p = 1.0 / 7.0;
+    p = fma(p, r, -1.0 / 6.0);
+    p = fma(p, r, 1.0 / 5.0);
+    p = fma(p, r, -1.0 / 4.0);
+    p = fma(p, r, 1.0 / 3.0);
+    p = fma(p, r, -1.0 / 2.0);
+    p = fma(p, r, 1.0);
+    const double l1p = p * r;
+    return -((fma((double)e, 0.69314718055994530942, lnc)) + l1p);
+}
 
 struct RunArgs {
     NetArgs net;
@@ -151,7 +179,71 @@ struct RunArgs {
     int64_t ldq;
     uint32_t qfloor;     // Q'_j = max(Q_j, qfloor, 1)
     uint32_t period;     // exact envelopes every period steps (0 or 1: every step)
+    const int4 *tab;     // [M][kDepMax] {jj, r0[jj], r1[jj], rate[jj] bits} of deps
+    const double *ln_tab;
 };
+
+// Uniform AR of one step on alpha in LDS with the envelope env: the rounds of
+// the sequential rule, trial t in Philox block t / 2 of the tag-2 stream
+// (words 0, 1 for even t, 2, 3 for odd t).  The first round's lane 63 draws
+// block 0xFFFFFFFE instead (the time step's), so that round covers blocks
+// 0..62 and round k >= 1 blocks 63 + 64 (k - 1) .. + 63; tau_w is word 0 of
+// block 0xFFFFFFFE.  After t_max trials the exact fallback runs.
+__device__ __forceinline__ Outcome ssa_uniform_rounds(const float *a, uint32_t M, float env,
+                                                      bool scanned, const Stream &st,
+                                                      uint32_t t_max, uint32_t &tau_w)
+{
+    const int lane = lane_id();
+    const uint32_t thresh = lemire_threshold(M);
+    const double envd = (double)env;
+    uint64_t key = kNoAccept;
+    uint32_t first = 0;      // first block of the round
+    bool round0 = true;
+    do {
+        const bool taul = round0 && lane == kWave - 1;
+        const uint32_t b = taul ? kTauBlock : first + (uint32_t)lane;
+        const Words w = st.block(b);
+        if (round0) tau_w = readlane_u32(w.w0, kWave - 1);
+        const uint64_t ta = 2 * (uint64_t)b;
+        uint32_t ja = 0, jb = 0;
+        const bool oka = !taul && lemire(w.w0, M, thresh, ja) && ta < t_max;
+        const bool okb = !taul && lemire(w.w2, M, thresh, jb) && ta + 1 < t_max;
+        const bool acca = oka && grid_u(w.w1) * envd < (double)a[ja];
+        const bool accb = okb && grid_u(w.w3) * envd < (double)a[jb];
+        const uint64_t ma = __ballot(acca), mb = __ballot(accb);
+        if (ma | mb) {
+            const int la = first_lane(ma), lb = first_lane(mb);
+            key = la <= lb ? ((2 * (uint64_t)(first + la)) << 32) | readlane_u32(ja, la)
+                           : ((2 * (uint64_t)(first + lb) + 1) << 32) | readlane_u32(jb, lb);
+        }
+        first += round0 ? kWave - 1 : kWave;
+        round0 = false;
+    } while (key == kNoAccept && 2 * (uint64_t)first < t_max);
+    if (key != kNoAccept) {
+        Outcome o;
+        o.index = (int32_t)(uint32_t)key;
+        o.trials = (uint32_t)(key >> 32) + 1;
+        o.alpha0 = 0.0f;
+        return o;
+    }
+    return wave_fallback(ContigAcc{a}, M, scanned, env, st, t_max, 0.0f);
+}
+
+// Row j of the packed dependency table: entry l < ndeps[j] holds reaction
+// jj = deps[j][l] with its reactants and rate, so the run's update reads one
+// 16-byte entry per affected reaction; other entries hold {-1, 0, -1, 0}.
+__global__ void k_ssa_pack(NetArgs n, const int32_t *deps, const int32_t *ndeps, int4 *tab)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n.M * kDepMax) return;
+    const int j = (int)(i / kDepMax), l = (int)(i % kDepMax);
+    int4 e = make_int4(-1, 0, -1, 0);
+    if (l < ndeps[j]) {
+        const int jj = deps[i];
+        e = make_int4(jj, n.r0[jj], n.r1[jj], __float_as_int(n.rate[jj]));
+    }
+    tab[i] = e;
+}
 
 // Valid propensity: non-negative (-0.0 included) and finite.
 __device__ __forceinline__ bool valid_prop(float v)
@@ -162,9 +254,8 @@ __device__ __forceinline__ bool valid_prop(float v)
 // Sum over the wavefront of two signed counts (|sum| < 2^31 each).
 __device__ __forceinline__ void wave_sum_pair(int32_t &a, int32_t &b)
 {
-    const uint64_t tot = wave_sum_u64((uint64_t)(int64_t)a + ((uint64_t)(int64_t)b << 32));
-    a = (int32_t)(uint32_t)tot;
-    b = (int32_t)(((int64_t)tot - (int64_t)a) >> 32);
+    a = (int32_t)wave_sum_u32((uint32_t)a);
+    b = (int32_t)wave_sum_u32((uint32_t)b);
 }
 
 // One wavefront per realization, counts and propensities in its LDS.  Each
@@ -264,11 +355,12 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
                 nbad = bad ? 1 : 0;
                 npos = B > 0.0f ? 1 : 0;
             }
-            a0 = wave_sum_f64(a0);
+            a0 = wave_sum_f64_dpp(a0);
             if (PROP && nbad == 0 && npos > 0 && sumq < (1ull << 32))
-                C = wave_proposal_c_band(a, (uint32_t)M, qat, wave_max(rmax));
+                C = wave_proposal_c_band(a, (uint32_t)M, qat, wave_max_f32_nonneg(rmax));
         }
         Outcome o;
+        uint32_t tau_w = 0;     // word 0 of the time step's Philox block
         if (nbad != 0) {
             o.index = -2;
         } else if (npos == 0) {
@@ -281,18 +373,12 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
                 const Stream sq = make_stream(c.seed, s, (uint32_t)r, kTagProposal);
                 o = wave_proposal_rounds(a, sp, (uint32_t)M, (uint32_t)sumq, cplus,
                                          exact ? B : -1.0f, sq, c.t_max);
+                tau_w = make_stream(c.seed, s, (uint32_t)r, kTagSSA).block(kTauBlock).w0;
             }
         } else {
-            ScanState ss;
-            ss.decided = false;
-            ss.scanned = exact;      // otherwise the fallback takes the exact maximum
-            ss.amax = B;
-            ss.env = B;
-            ss.o.alpha0 = 0.0f;
-            ss.o.trials = 0;
-            ss.o.index = -1;
-            o = wave_run(ContigAcc{a}, (uint32_t)M, ss, make_stream(c.seed, s, (uint32_t)r, kTagSSA),
-                         c.t_max);
+            // at a non-exact step the fallback takes the exact maximum itself
+            o = ssa_uniform_rounds(a, (uint32_t)M, B, exact,
+                                   make_stream(c.seed, s, (uint32_t)r, kTagSSA), c.t_max, tau_w);
         }
         const int32_t j = (int32_t)uniform_u32((uint32_t)o.index);
         if (c.fired && lane == 0) c.fired[i * c.R + r] = j;
@@ -300,11 +386,9 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
             // reaction j's stoichiometry, dependency count and whole dependency
             // row (in bounds: the table is [M][kDepMax]) issued together
             const int32_t nd = c.ndeps[j];
-            const int32_t dl = c.deps[(int64_t)j * kDepMax + lane];
+            const int4 dl = c.tab[(int64_t)j * kDepMax + lane];
             const int32_t jr0 = c.net.r0[j], jr1 = c.net.r1[j], jp0 = c.net.p0[j], jp1 = c.net.p1[j];
-            const Words w = make_stream(c.seed, s, (uint32_t)r, kTagSSA).block(kTauBlock);
-            const double u = ((double)w.w0 + 0.5) * 0x1p-32;
-            t += log(1.0 / u) / a0;
+            t += neg_ln_u(uniform_u32(tau_w), c.ln_tab) / a0;
             if (lane == 0) {
                 x[jr0] -= 1;
                 if (jr1 >= 0) x[jr1] -= 1;
@@ -312,43 +396,51 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
                 if (jp1 >= 0) x[jp1] += 1;
             }
             wave_sync_lds();
-            int32_t dpos = 0, dbad = 0;
-            double da0 = 0.0, cm = 0.0;
-            uint32_t bm = 0;
-            auto update = [&](int jj) {
-                const float old = a[jj];
-                const float nv = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
-                a[jj] = nv;
-                dpos += (int32_t)(nv > 0.0f) - (int32_t)(old > 0.0f);
-                dbad += (int32_t)!valid_prop(nv) - (int32_t)!valid_prop(old);
-                da0 += (double)nv - (double)old;
-                if (valid_prop(nv)) {
-                    if (!PROP) bm = max(bm, __float_as_uint(nv) & 0x7FFFFFFFu);
-                    if (PROP && nv > 0.0f) cm = fmax(cm, (double)nv / (double)qat((uint32_t)jj));
-                }
-            };
             if (maintain) {
-                if (nd < 0) {
-                    for (int jj = lane; jj < M; jj += kWave) update(jj);
-                } else if (lane < nd) {
-                    update(dl);
-                }
-                wave_sum_pair(dpos, dbad);
-                npos += dpos;
-                nbad += dbad;
-                a0 += wave_sum_f64(da0);
-                if (PROP)
-                    C = fmax(C, wave_max_f64(cm));
-                else
-                    B = fmaxf(B, __uint_as_float(wave_max_u32(bm)));
-            } else {
-                auto set = [&](int jj) {
-                    a[jj] = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+                // count changes from ballots (wave-uniform), alpha_0 from the
+                // lanes' differences, the envelope only when a new value
+                // exceeds it
+                double da0 = 0.0, cm = 0.0;
+                uint32_t bm = 0;
+                auto update = [&](bool on, int jj, int32_t ra, int32_t rb, float k) {
+                    float old = 0.0f, nv = 0.0f;
+                    if (on) {
+                        old = a[jj];
+                        nv = mass_action(x, ra, rb, k);
+                        a[jj] = nv;
+                        da0 += (double)nv - (double)old;
+                        if (valid_prop(nv)) {
+                            if (!PROP) bm = max(bm, __float_as_uint(nv) & 0x7FFFFFFFu);
+                            if (PROP && nv > 0.0f)
+                                cm = fmax(cm, (double)nv / (double)qat((uint32_t)jj));
+                        }
+                    }
+                    npos += __popcll(__ballot(on && nv > 0.0f)) - __popcll(__ballot(on && old > 0.0f));
+                    nbad += __popcll(__ballot(on && !valid_prop(nv))) -
+                            __popcll(__ballot(on && !valid_prop(old)));
                 };
                 if (nd < 0) {
-                    for (int jj = lane; jj < M; jj += kWave) set(jj);
+                    for (int base = 0; base < M; base += kWave) {
+                        const int jj = base + lane;
+                        const bool on = jj < M;
+                        update(on, jj, on ? c.net.r0[jj] : 0, on ? c.net.r1[jj] : -1,
+                               on ? c.net.rate[jj] : 0.0f);
+                    }
+                } else {
+                    update(lane < nd, dl.x, dl.y, dl.z, __int_as_float(dl.w));
+                }
+                a0 += (nd >= 0 && nd <= 16) ? row0_sum_f64(da0) : wave_sum_f64_dpp(da0);
+                if (PROP) {
+                    if (__ballot(cm > C)) C = fmax(C, wave_max_f64_nonneg(cm));
+                } else {
+                    if (__ballot(bm > __float_as_uint(B))) B = fmaxf(B, __uint_as_float(wave_max_u32(bm)));
+                }
+            } else {
+                if (nd < 0) {
+                    for (int jj = lane; jj < M; jj += kWave)
+                        a[jj] = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
                 } else if (lane < nd) {
-                    set(dl);
+                    a[dl.x] = mass_action(x, dl.y, dl.z, __int_as_float(dl.w));
                 }
             }
             wave_sync_lds();
@@ -445,8 +537,21 @@ static int ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps
     if ((rc = ctx_activate(ctx))) return rc;
     const size_t per_wave = (size_t)(net->N + (prop ? 2 : 1) * (size_t)net->M) * 4;
     if (per_wave > ctx->lds_per_block) return ARSEL_ERR_SIZE;
-    RunArgs c{net_args(net), deps, ndeps, X, R, seed, step0, steps, t_max, t, times, fired, Q, ldq, qfloor, period};
+    const size_t tab_bytes = (size_t)net->M * kDepMax * sizeof(int4);
+    if (ctx->ssa_tab_bytes < tab_bytes) {
+        if (ctx->ssa_tab && hipFree(ctx->ssa_tab) != hipSuccess) return ARSEL_ERR_HIP;
+        ctx->ssa_tab = nullptr;
+        ctx->ssa_tab_bytes = 0;
+        if (hipMalloc(&ctx->ssa_tab, tab_bytes) != hipSuccess) return ARSEL_ERR_ALLOC;
+        ctx->ssa_tab_bytes = tab_bytes;
+    }
+    int4 *tab = (int4 *)ctx->ssa_tab;
     hipStream_t s = (hipStream_t)stream;
+    const int64_t entries = (int64_t)net->M * kDepMax;
+    hipLaunchKernelGGL(k_ssa_pack, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s,
+                       net_args(net), deps, ndeps, tab);
+    RunArgs c{net_args(net), deps, ndeps, X, R, seed, step0, steps, t_max, t, times, fired, Q, ldq,
+              qfloor, period, tab, ctx->ln_tab};
     const bool four = per_wave * 4 <= ctx->tile_lds_bytes;
     const dim3 grid(four ? (R + 3) / 4 : R), block(four ? 256 : 64);
     const size_t lds = per_wave * (four ? 4 : 1);
