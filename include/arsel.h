@@ -247,6 +247,11 @@ int arsel_ssa_deps(arsel_ctx *ctx, const arsel_network *net, int32_t *deps, int3
  * only its candidates and the changed reactions.  Results depend on where
  * calls start, except when they start at multiples of period.
  *
+ * Each call first writes a packed copy of the dependency rows ({jj, reactants,
+ * rate} per entry) into a buffer of the context (grown on demand, so the first
+ * call with a larger M allocates): runs of different networks on one context
+ * must not overlap on different streams.
+ *
  * An invalid propensity (NaN, negative, +inf) records -2 and no positive one
  * -1; the state and time then stay.  fired (nullable, [steps][R]) and times
  * (nullable, [steps][R], t after each step) are outputs.  States and
