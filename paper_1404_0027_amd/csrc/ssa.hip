@@ -451,6 +451,266 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
     if (lane == 0) c.t[r] = t;
 }
 
+// ---- two realizations per wavefront (uniform AR) ----
+//
+// Half h of a wavefront (lanes 32h .. 32h + 31) runs realization 2w + h with
+// the steps of k_ssa_run<NW, false>, each half doing what the whole wave
+// does there; the results are identical (same trials, same fallback, same
+// envelopes).  One wavefront's instruction stream then serves two
+// realizations, which pays because that kernel's step is issue-bound.
+// Rounds cover 32 Philox blocks per half (the first round 31 trial blocks
+// and the time step's block in lane 31 of the half).
+
+// Sums / maxima over each half by DPP row shifts and one row broadcast: half
+// 0's total ends in lane 31, half 1's in lane 63; every lane returns its
+// half's.
+__device__ __forceinline__ uint32_t half_pick(uint32_t v0, uint32_t v1)
+{
+    return (lane_id() & 32) ? v1 : v0;
+}
+
+__device__ __forceinline__ uint32_t half_sum_u32(uint32_t x)
+{
+    x += dpp_u32<0x111>(x);
+    x += dpp_u32<0x112>(x);
+    x += dpp_u32<0x114>(x);
+    x += dpp_u32<0x118>(x);
+    x += dpp_u32<0x142, 0xA>(x);     // row_bcast:15 into rows 1 and 3
+    return half_pick((uint32_t)__builtin_amdgcn_readlane((int)x, 31),
+                     (uint32_t)__builtin_amdgcn_readlane((int)x, 63));
+}
+
+__device__ __forceinline__ uint32_t half_max_u32(uint32_t x)
+{
+    x = max(x, dpp_u32<0x111>(x));
+    x = max(x, dpp_u32<0x112>(x));
+    x = max(x, dpp_u32<0x114>(x));
+    x = max(x, dpp_u32<0x118>(x));
+    x = max(x, dpp_u32<0x142, 0xA>(x));
+    return half_pick((uint32_t)__builtin_amdgcn_readlane((int)x, 31),
+                     (uint32_t)__builtin_amdgcn_readlane((int)x, 63));
+}
+
+__device__ __forceinline__ double half_sum_f64(double x)
+{
+    auto bits = [](double v) { return (uint64_t)__double_as_longlong(v); };
+    auto dbl = [](uint64_t b) { return __longlong_as_double((long long)b); };
+    x += dbl(dpp_u64<0x111>(bits(x)));
+    x += dbl(dpp_u64<0x112>(bits(x)));
+    x += dbl(dpp_u64<0x114>(bits(x)));
+    x += dbl(dpp_u64<0x118>(bits(x)));
+    x += dbl(dpp_u64<0x142, 0xA>(bits(x)));
+    const uint64_t b = bits(x);
+    const uint32_t lo = half_pick((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 31),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63));
+    const uint32_t hi = half_pick((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 31),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63));
+    return dbl((uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+// 64-bit shuffles within the 32-lane half (the fallback's rare path).
+__device__ __forceinline__ uint64_t half_shfl_xor_u64(uint64_t x, int off)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, off, 32);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), off, 32);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__device__ __forceinline__ uint64_t half_shfl_up_u64(uint64_t x, int d)
+{
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 32);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 32);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// The exact fixed-point inverse transform of one half's instance (valid
+// propensities, at least one positive): the arithmetic of wave_fallback over
+// 32 lanes.  Called by the lanes of the halves that need it (whole halves).
+__device__ int32_t half_fallback(const float *a, uint32_t M, const Stream &st)
+{
+    const int hl = lane_id() & 31;
+    uint32_t mb = 0;
+    for (uint32_t j = hl; j < M; j += 32) mb = max(mb, __float_as_uint(a[j]) & 0x7FFFFFFFu);
+#pragma unroll
+    for (int off = 16; off >= 1; off >>= 1) mb = max(mb, (uint32_t)__shfl_xor((int)mb, off, 32));
+    const int shift = 63 - ceil_log2_u32(M) - exponent_above(__uint_as_float(mb));
+    uint64_t S = 0;
+    for (uint32_t j = hl; j < M; j += 32) S += fixed_weight(a[j], shift);
+#pragma unroll
+    for (int off = 16; off >= 1; off >>= 1) S += half_shfl_xor_u64(S, off);
+    const Words w = st.block(kFallbackBlock);
+    const uint64_t target = umul64hi((uint64_t)w.w0 | ((uint64_t)w.w1 << 32), S);
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < M; base += 32) {
+        const uint32_t j = base + hl;
+        const uint64_t f = j < M ? fixed_weight(a[j], shift) : 0;
+        uint64_t incl = f;
+#pragma unroll
+        for (int d = 1; d < 32; d <<= 1) {
+            const uint64_t u = half_shfl_up_u64(incl, d);
+            if (hl >= d) incl += u;
+        }
+        incl += carry;
+        const uint32_t hit = (uint32_t)(__ballot(j < M && incl > target) >> (lane_id() & 32));
+        if (hit) return (int32_t)(base + __builtin_ctz(hit));
+        const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)incl, 31, 32);
+        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(incl >> 32), 31, 32);
+        carry = (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+    return -1;  // unreachable for S > 0
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
+{
+    extern __shared__ int32_t lds_i[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int h = lane >> 5, hl = lane & 31;
+    const int rw = (blockIdx.x * NW + wave) * 2;
+    if (rw >= c.R) return;
+    const int r = rw + h;
+    const bool live = r < c.R;          // the last wavefront may hold one realization
+    const int N = c.net.N, M = c.net.M;
+    int32_t *x = lds_i + ((size_t)wave * 2 + h) * (N + M);
+    float *a = reinterpret_cast<float *>(x + N);
+    int32_t *gx = c.X + (int64_t)r * N;
+    if (live)
+        for (int i = hl; i < N; i += 32) x[i] = gx[i];
+    wave_sync_lds();
+    for (int j = hl; j < M; j += 32)
+        a[j] = live ? mass_action(x, c.net.r0[j], c.net.r1[j], c.net.rate[j]) : 0.0f;
+    wave_sync_lds();
+    const uint64_t period = max(c.period, 1u);
+    const bool maintain = period > 1;
+    double t = live ? c.t[r] : 0.0;
+    double a0 = 0.0;
+    float B = 0.0f;
+    int32_t npos = 0, nbad = 0;
+    const uint32_t thresh = lemire_threshold((uint32_t)M);
+    for (int64_t i = 0; i < c.steps; ++i) {
+        const uint64_t s = c.step0 + (uint64_t)i;
+        const bool exact = i == 0 || s % period == 0;
+        if (exact) {
+            uint32_t mb = 0, cnt = 0;
+            double ap = 0.0;
+            for (int j = hl; j < M; j += 32) {
+                const float v = a[j];
+                mb = max(mb, __float_as_uint(v) & 0x7FFFFFFFu);
+                ap += (double)v;
+                cnt += (uint32_t)(v > 0.0f) + ((uint32_t)!valid_prop(v) << 16);
+            }
+            B = __uint_as_float(half_max_u32(mb));
+            a0 = half_sum_f64(ap);
+            cnt = half_sum_u32(cnt);
+            npos = live ? (int32_t)(cnt & 0xFFFFu) : 0;
+            nbad = live ? (int32_t)(cnt >> 16) : 0;
+        }
+        // the step's selection: -2 / -1 decided, else the rounds
+        int32_t j = nbad ? -2 : -1;
+        bool open = live && nbad == 0 && npos > 0;
+        const Stream st = make_stream(c.seed, s, (uint32_t)r, kTagSSA);
+        uint32_t tau_w = 0;
+        {
+            const double envd = (double)B;
+            uint32_t first = 0;
+            bool round0 = true;
+            do {
+                const bool taul = round0 && hl == 31;
+                const uint32_t b = taul ? kTauBlock : first + (uint32_t)hl;
+                const Words w = st.block(b);
+                if (round0)
+                    tau_w = half_pick((uint32_t)__builtin_amdgcn_readlane((int)w.w0, 31),
+                                      (uint32_t)__builtin_amdgcn_readlane((int)w.w0, 63));
+                const uint64_t ta = 2 * (uint64_t)b;
+                uint32_t ja = 0, jb = 0;
+                const bool oka = open && !taul && lemire(w.w0, (uint32_t)M, thresh, ja) && ta < c.t_max;
+                const bool okb = open && !taul && lemire(w.w2, (uint32_t)M, thresh, jb) && ta + 1 < c.t_max;
+                const bool acca = oka && grid_u(w.w1) * envd < (double)a[ja];
+                const bool accb = okb && grid_u(w.w3) * envd < (double)a[jb];
+                const uint64_t ma = __ballot(acca), mbb = __ballot(accb);
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const uint32_t mah = (uint32_t)(ma >> (32 * hh)), mbh = (uint32_t)(mbb >> (32 * hh));
+                    if (mah | mbh) {
+                        const int la = mah ? __builtin_ctz(mah) : 64;
+                        const int lb = mbh ? __builtin_ctz(mbh) : 64;
+                        const int32_t jh = la <= lb
+                            ? (int32_t)__builtin_amdgcn_readlane((int)ja, 32 * hh + la)
+                            : (int32_t)__builtin_amdgcn_readlane((int)jb, 32 * hh + lb);
+                        if (h == hh) {
+                            j = jh;
+                            open = false;
+                        }
+                    }
+                }
+                first += round0 ? 31u : 32u;
+                round0 = false;
+            } while (__ballot(open) && 2 * (uint64_t)first < c.t_max);
+        }
+        if (open) j = half_fallback(a, (uint32_t)M, st);
+        if (c.fired && live && hl == 0) c.fired[i * c.R + r] = j;
+        const bool fire = live && j >= 0;
+        if (__ballot(fire)) {
+            const int jf = fire ? j : 0;
+            const int32_t nd = fire ? c.ndeps[jf] : 0;
+            const int4 d0 = c.tab[(int64_t)jf * kDepMax + hl];
+            const int4 d1 = c.tab[(int64_t)jf * kDepMax + 32 + hl];
+            const int32_t jr0 = c.net.r0[jf], jr1 = c.net.r1[jf], jp0 = c.net.p0[jf], jp1 = c.net.p1[jf];
+            if (fire) t += neg_ln_u(tau_w, c.ln_tab) / a0;
+            if (fire && hl == 0) {
+                x[jr0] -= 1;
+                if (jr1 >= 0) x[jr1] -= 1;
+                x[jp0] += 1;
+                if (jp1 >= 0) x[jp1] += 1;
+            }
+            wave_sync_lds();
+            const bool full = fire && nd < 0;
+            if (maintain) {
+                double da0 = 0.0;
+                uint32_t bm = 0;
+                int32_t dpos = 0, dbad = 0;
+                auto update = [&](int jj, int32_t ra, int32_t rb, float k) {
+                    const float old = a[jj];
+                    const float nv = mass_action(x, ra, rb, k);
+                    a[jj] = nv;
+                    da0 += (double)nv - (double)old;
+                    if (valid_prop(nv)) bm = max(bm, __float_as_uint(nv) & 0x7FFFFFFFu);
+                    dpos += (int32_t)(nv > 0.0f) - (int32_t)(old > 0.0f);
+                    dbad += (int32_t)!valid_prop(nv) - (int32_t)!valid_prop(old);
+                };
+                if (full) {
+                    for (int jj = hl; jj < M; jj += 32) update(jj, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+                } else if (fire) {
+                    if (hl < nd) update(d0.x, d0.y, d0.z, __int_as_float(d0.w));
+                    if (32 + hl < nd) update(d1.x, d1.y, d1.z, __int_as_float(d1.w));
+                }
+                // signed counts packed as dpos + 2^16 dbad (|sums| <= M < 2^15)
+                const int32_t tot = (int32_t)half_sum_u32((uint32_t)(dpos + dbad * 65536));
+                const int32_t sp = (int32_t)(int16_t)(tot & 0xFFFF);
+                npos += sp;
+                nbad += (tot - sp) / 65536;
+                a0 += half_sum_f64(da0);
+                if (__ballot(bm > __float_as_uint(B))) B = fmaxf(B, __uint_as_float(half_max_u32(bm)));
+            } else {
+                if (full) {
+                    for (int jj = hl; jj < M; jj += 32)
+                        a[jj] = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+                } else if (fire) {
+                    if (hl < nd) a[d0.x] = mass_action(x, d0.y, d0.z, __int_as_float(d0.w));
+                    if (32 + hl < nd) a[d1.x] = mass_action(x, d1.y, d1.z, __int_as_float(d1.w));
+                }
+            }
+            wave_sync_lds();
+        }
+        if (c.times && live && hl == 0) c.times[i * c.R + r] = t;
+    }
+    if (live) {
+        for (int i = hl; i < N; i += 32) gx[i] = x[i];
+        if (hl == 0) c.t[r] = t;
+    }
+}
+
 static int check_net(const arsel_network *n)
 {
     if (!n || !n->r0 || !n->r1 || !n->p0 || !n->p1 || !n->rate) return ARSEL_ERR_NULL;
@@ -552,6 +812,23 @@ static int ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps
                        net_args(net), deps, ndeps, tab);
     RunArgs c{net_args(net), deps, ndeps, X, R, seed, step0, steps, t_max, t, times, fired, Q, ldq,
               qfloor, period, tab, ctx->ln_tab};
+    // uniform runs with maintained envelopes: two realizations per wavefront when two
+    // fit in one workgroup's LDS (and the packed counts of the exact pass fit their
+    // 16-bit fields).  With period 1 the exact pass runs every step, and over 32
+    // lanes it costs more than the pairing saves (measured), so one per wavefront.
+    if (!prop && period > 1 && net->M < (1 << 15) && 2 * per_wave <= ctx->lds_per_block) {
+        int nw = 4;
+        while (nw > 1 && 2 * per_wave * nw > ctx->tile_lds_bytes) nw >>= 1;
+        const int pairs = (R + 1) / 2;
+        const dim3 pgrid((pairs + nw - 1) / nw), pblock(64 * nw);
+        const size_t plds = 2 * per_wave * nw;
+        switch (nw) {
+        case 4: hipLaunchKernelGGL(k_ssa_run_pair<4>, pgrid, pblock, plds, s, c); break;
+        case 2: hipLaunchKernelGGL(k_ssa_run_pair<2>, pgrid, pblock, plds, s, c); break;
+        default: hipLaunchKernelGGL(k_ssa_run_pair<1>, pgrid, pblock, plds, s, c); break;
+        }
+        return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+    }
     const bool four = per_wave * 4 <= ctx->tile_lds_bytes;
     const dim3 grid(four ? (R + 3) / 4 : R), block(four ? 256 : 64);
     const size_t lds = per_wave * (four ? 4 : 1);

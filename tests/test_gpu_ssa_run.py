@@ -55,8 +55,10 @@ def _run_both(net, X0, *, seed, step0, steps, want_times=True, period=1, t_max=4
 
 
 @pytest.mark.parametrize("period", [1, 7, 64])
-@pytest.mark.parametrize("N,M,R,steps", [(64, 100, 40, 300), (641, 1029, 64, 200)])
+@pytest.mark.parametrize("N,M,R,steps", [(64, 100, 40, 300), (641, 1029, 64, 200), (64, 100, 37, 150),
+                                         (64, 100, 1, 150), (641, 1029, 9, 100)])
 def test_run_matches_oracle(gpu, N, M, R, steps, period):
+    """Two realizations share a wavefront: odd R leaves the last one alone."""
     net = workloads.mass_action_network(N=N, M=M, seed=4)
     X0 = workloads.poisson_counts(N=N, R=R, seed=5)
     _run_both(net, X0, seed=3, step0=11, steps=steps, period=period)
@@ -197,8 +199,9 @@ def test_run_with_proposal_budgets_and_padding(gpu, t_max):
     Q = _shaped_q(net, X0)
     _run_both_q(net, X0, Q, seed=5, step0=2, steps=120, t_max=t_max, ldq=107)
     _run_both_q(net, X0, Q, seed=5, step0=2, steps=120, t_max=t_max, ldq=107, period=50)
-    if t_max <= 1:    # the uniform run's fallback with maintained bounds too
-        _run_both(net, X0, seed=5, step0=2, steps=120, period=50, t_max=t_max)
+    # the uniform run's fallback, with exact and maintained envelopes, odd R
+    _run_both(net, X0, seed=5, step0=2, steps=120, period=50, t_max=t_max)
+    _run_both(net, X0[:47], seed=6, step0=2, steps=120, period=1, t_max=t_max)
 
 
 def test_run_with_proposal_overflow_and_absorption(gpu):
