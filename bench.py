@@ -348,23 +348,34 @@ def bench_paper_table1(torch, np, arsel, workloads):
                     "the multinomial sampling floor, the paper's scheme adds its bias"}
 
 
-def bench_scale(torch):
-    """The dense kernel at the paper's scale claim: 10^6 realizations x M = 1029
-    (SoA, lognormal(0,2) with 30% zeros, 4.1 GB) in one launch."""
-    Mb, Kb = 1029, 1_000_000
-    g = torch.Generator(device="cuda").manual_seed(123)
-    a = torch.empty(Mb, Kb, device="cuda").log_normal_(0.0, 2.0, generator=g)
-    a[torch.rand(Mb, Kb, device="cuda", generator=g) < 0.3] = 0.0
-    idx = torch.empty(Kb, dtype=torch.int32, device="cuda")
+def _scale_input(torch, M: int, K: int, seed: int):
+    """SoA [M][K] lognormal(0,2) with 30% exact zeros, generated on the GPU in
+    row chunks (no [M][K] temporary)."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    a = torch.empty(M, K, device="cuda")
+    for r in range(0, M, 64):
+        blk = a[r:r + 64]
+        blk.log_normal_(0.0, 2.0, generator=g)
+        blk[torch.rand(blk.shape, device="cuda", generator=g) < 0.3] = 0.0
+    return a
+
+
+def bench_scale(torch, K: int = 1_000_000, reps: int = 10):
+    """The dense kernel at the paper's scale claims: K realizations x M = 1029
+    (SoA, lognormal(0,2) with 30% zeros) in one launch -- 10^6 (4.1 GB), and
+    the sensitivity-analysis shape 9 x 1029 x 1000 = 9,261,000 (38 GB)."""
     from paper_1404_0027_amd import arsel
 
-    sec = _timed(torch, lambda s: arsel.select(a, Mb, Kb, Kb, arsel.SOA, seed=SEED, step=s,
-                                                index=idx), 10)
-    nbytes = Kb * (4 * Mb + 4)
+    Mb = 1029
+    a = _scale_input(torch, Mb, K, 123)
+    idx = torch.empty(K, dtype=torch.int32, device="cuda")
+    sec = _timed(torch, lambda s: arsel.select(a, Mb, K, K, arsel.SOA, seed=SEED, step=s,
+                                                index=idx), reps)
+    nbytes = K * (4 * Mb + 4)
     del a
     torch.cuda.empty_cache()
-    return {"workload": f"{Kb} realizations x M={Mb} SoA (lognormal(0,2), 30% zeros), one launch",
-            "selections_per_s": round(Kb / sec, 1), "us_per_launch": round(sec * 1e6, 1),
+    return {"workload": f"{K} realizations x M={Mb} SoA (lognormal(0,2), 30% zeros), one launch",
+            "selections_per_s": round(K / sec, 1), "us_per_launch": round(sec * 1e6, 1),
             "algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / sec / 1e9, 1),
             "frac_of_8TBs": round(nbytes / sec / 1e9 / HBM_PEAK_GBS, 4)}
 
@@ -462,7 +473,7 @@ def main() -> int:
         cpu, parity = cpu_baseline(host, threads=min(16, os.cpu_count() or 1), last_step=last,
                                    gpu_index=got)
 
-    ragged = learned_res = ssa_res = paper_res = scale_res = None
+    ragged = learned_res = ssa_res = paper_res = scale_res = sens_res = None
     if not args.no_extras:
         print("[bench] uneven batch", file=sys.stderr, flush=True)
         ragged = bench_ragged(torch, arsel, workloads)
@@ -475,6 +486,9 @@ def main() -> int:
         paper_res = bench_paper_table1(torch, np, arsel, workloads)
         print("[bench] 10^6 realizations in one launch", file=sys.stderr, flush=True)
         scale_res = bench_scale(torch)
+        print("[bench] sensitivity-analysis shape: 9,261,000 realizations", file=sys.stderr,
+              flush=True)
+        sens_res = bench_scale(torch, K=9 * 1029 * 1000, reps=3)
         acceptance["learned_per_trial"] = learned_res["per_state"]["acceptance_per_trial"]["learned"]
         acceptance["uniform_per_trial_same_states"] = (
             learned_res["per_state"]["acceptance_per_trial"]["uniform"])
@@ -498,6 +512,7 @@ def main() -> int:
         "ssa_run": ssa_res,
         "paper_table1": paper_res,
         "scale_1e6": scale_res,
+        "sensitivity_9x1029x1000": sens_res,
     }
     print(json.dumps(out), flush=True)
     return 1 if parity.startswith("MISMATCH") else 0

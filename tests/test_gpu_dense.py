@@ -201,3 +201,26 @@ def test_graph_replays_match_eager(gpu):
         torch.cuda.synchronize()
         assert torch.equal(out, eager), rep
         arsel.select(bufs[0], M, K, K, SOA, seed=9, step=99, index=eager[0].clone())   # eager work between
+
+
+def test_sensitivity_analysis_shape_sampled(gpu):
+    """9 x 1029 x 1000 = 9,261,000 realizations x M = 1029 (SoA, 38 GB) in one
+    launch, element offsets far beyond 2^32; sampled instances (and the ragged
+    last tile) checked against the oracle by instance id."""
+    M, K = 1029, 9 * 1029 * 1000
+    g = torch.Generator(device="cuda").manual_seed(321)
+    a = torch.empty(M, K, device="cuda")
+    for r in range(0, M, 64):
+        blk = a[r:r + 64]
+        blk.log_normal_(0.0, 2.0, generator=g)
+        blk[torch.rand(blk.shape, device="cuda", generator=g) < 0.3] = 0.0
+    idx, a0, tr = arsel.select(a, M, K, K, arsel.SOA, seed=9, step=5, want_alpha0=True,
+                               want_trials=True)
+    ids = np.unique(np.r_[np.random.default_rng(1).choice(K, 64, replace=False), 0, K - 2, K - 1])
+    rows = a[:, torch.from_numpy(ids.astype(np.int64)).cuda()].T.contiguous().cpu().numpy()
+    oi, oa, ot = oracle.select_ids(rows, ids.astype(np.uint32), seed=9, step=5, threads=8)
+    assert np.array_equal(idx.cpu().numpy()[ids], oi)
+    assert np.array_equal(tr.cpu().numpy().view(np.uint32)[ids], ot)
+    assert np.array_equal(a0.cpu().numpy()[ids].view(np.uint32), oa.view(np.uint32))
+    del a
+    torch.cuda.empty_cache()
