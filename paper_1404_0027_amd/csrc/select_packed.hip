@@ -13,11 +13,13 @@
 //
 // Each trial costs one half Philox block whatever L is; a wide group wastes
 // the trials after the first accepted one in its round, a narrow one spends
-// more rounds.  With one lane per instance (L = 1) no trial is wasted beyond
-// the accepted one and its twin, so the Philox work per selection is about
-// 1 / (2 p) blocks for per-trial acceptance p -- which is what a proposal
-// close to alpha / alpha_0 (p near 1) turns into a large speed-up.  Wider
-// groups finish a single instance sooner (latency) when K is small.
+// more rounds, hands out instances more often and waits longer for the last
+// one of a workgroup.  With one lane per instance (L = 1) no trial is wasted
+// beyond the accepted one and its twin, so the Philox work per selection is
+// about 1 / (2 p) blocks for per-trial acceptance p -- the width a proposal
+// close to alpha / alpha_0 (p near 1) runs at.  For small p the automatic
+// width grows to about 1 / (2 p) lanes (the expected trials of a selection
+// in one round); for small K it grows until every lane has an instance.
 #include "launch.hpp"
 #include "select_block.hpp"
 
@@ -66,6 +68,19 @@ __device__ __forceinline__ uint32_t guide_pick(const uint32_t *P, const uint32_t
     uint32_t j = G[(uint32_t)((uint64_t)V >> gs)];   // gs may be 32 (M = 1)
     while (P[j] <= V) ++j;
     return j;
+}
+
+// Claim v (wave-uniform) instances from the workgroup cursor: lane 0 alone
+// performs the LDS atomic and its old value is broadcast.  (An atomic issued
+// by every lane with a per-lane value -- lane 0's v, 0 elsewhere -- is turned
+// by the compiler into a scan over the active lanes, one lane per iteration,
+// which made this claim cost more than a round of trials.)  Called by a
+// converged wavefront.
+__device__ __forceinline__ uint32_t claim_instances(uint32_t *cursor, uint32_t v)
+{
+    uint32_t old = 0;
+    if (lane_id() == 0) old = atomicAdd(cursor, v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)old, 0);
 }
 
 struct PackedShared {
@@ -188,14 +203,17 @@ __global__ __launch_bounds__(NW * 64) void k_select_packed(PackedArgs a)
         sh.alpha0 = alpha0;
         sh.env = env;
         sh.cursor = (uint32_t)k_lo;
-        // trial width: as given, else no wider than the expected trials per
-        // selection (1 / p) and no wider than needed to give every lane work
+        // trial width: as given, else as wide as the expected trials per
+        // selection (1 / p) use, and at least as wide as gives every lane of
+        // the launch an instance (measured: with 2^20 uniform-AR instances,
+        // p ~ 0.05, 8 lanes per instance run 2x faster than 1 -- fewer
+        // instance hand-offs and a shorter tail per round of trials)
         int l2 = 0;
         if (a.lanes > 0) {
             l2 = 31 - __clz(a.lanes);
         } else if (status == 0) {
             const double want = phat > 0.0 ? 0.5 / phat : 64.0;
-            while (l2 < 6 && (double)(2 << l2) <= want && (1 << (l2 + 1)) <= a.fill_lanes) ++l2;
+            while (l2 < 6 && ((double)(2 << l2) <= want || (1 << (l2 + 1)) <= a.fill_lanes)) ++l2;
         }
         sh.lanes_log2 = (uint32_t)l2;
     }
@@ -236,7 +254,7 @@ __global__ __launch_bounds__(NW * 64) void k_select_packed(PackedArgs a)
         const uint64_t lead = __ballot(gl == 0 && inst < 0);
         if (!exhausted && lead != 0) {
             const uint32_t want = (uint32_t)__popcll(lead);
-            const uint32_t base = wave_fetch_add(&sh.cursor, want);
+            const uint32_t base = claim_instances(&sh.cursor, want);
             if (base + want >= (uint32_t)k_hi) exhausted = true;
             if (inst < 0) {
                 const uint32_t rank = (uint32_t)__popcll(lead & ((1ull << gbase) - 1));
