@@ -22,6 +22,7 @@
 // in one round); for small K it grows until every lane has an instance.
 #include "launch.hpp"
 #include "select_block.hpp"
+#include "wave_reduce.hpp"
 
 namespace arsel {
 
@@ -68,19 +69,6 @@ __device__ __forceinline__ uint32_t guide_pick(const uint32_t *P, const uint32_t
     uint32_t j = G[(uint32_t)((uint64_t)V >> gs)];   // gs may be 32 (M = 1)
     while (P[j] <= V) ++j;
     return j;
-}
-
-// Claim v (wave-uniform) instances from the workgroup cursor: lane 0 alone
-// performs the LDS atomic and its old value is broadcast.  (An atomic issued
-// by every lane with a per-lane value -- lane 0's v, 0 elsewhere -- is turned
-// by the compiler into a scan over the active lanes, one lane per iteration,
-// which made this claim cost more than a round of trials.)  Called by a
-// converged wavefront.
-__device__ __forceinline__ uint32_t claim_instances(uint32_t *cursor, uint32_t v)
-{
-    uint32_t old = 0;
-    if (lane_id() == 0) old = atomicAdd(cursor, v);
-    return (uint32_t)__builtin_amdgcn_readlane((int)old, 0);
 }
 
 struct PackedShared {
@@ -254,7 +242,7 @@ __global__ __launch_bounds__(NW * 64) void k_select_packed(PackedArgs a)
         const uint64_t lead = __ballot(gl == 0 && inst < 0);
         if (!exhausted && lead != 0) {
             const uint32_t want = (uint32_t)__popcll(lead);
-            const uint32_t base = claim_instances(&sh.cursor, want);
+            const uint32_t base = wave_claim_add(&sh.cursor, want);
             if (base + want >= (uint32_t)k_hi) exhausted = true;
             if (inst < 0) {
                 const uint32_t rank = (uint32_t)__popcll(lead & ((1ull << gbase) - 1));

@@ -15,6 +15,7 @@
 
 #include "launch.hpp"
 #include "select_block.hpp"
+#include "wave_reduce.hpp"
 
 namespace arsel {
 
@@ -128,11 +129,11 @@ __global__ __launch_bounds__(NW * 64) void k_select_ragged(RaggedArgs a)
     float *slice = lds + (size_t)wave * a.wave_max_m;
     // Same prefetch of the next item, per wavefront: the claim's old value
     // stays in a register until the current item is done.
-    uint32_t claim = atomicAdd(&a.queue[1], lane == 0 ? 1u : 0u);
+    uint32_t claim = wave_claim_add(&a.queue[1], 1u);
     for (;;) {
         const uint32_t i = uniform_u32(claim);
         if (i >= n_wave) break;
-        claim = atomicAdd(&a.queue[1], lane == 0 ? 1u : 0u);
+        claim = wave_claim_add(&a.queue[1], 1u);
         const int k = a.list_wave[i];
         const int64_t off = a.offsets[k];
         const int64_t m64 = a.offsets[k + 1] - off;

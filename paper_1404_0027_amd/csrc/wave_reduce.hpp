@@ -79,4 +79,18 @@ __device__ __forceinline__ float wave_max_f32_nonneg(float x)
     return __uint_as_float(wave_max_u32(__float_as_uint(x)));
 }
 
+// Fetch-and-add of a wave-uniform v by the wavefront: the first active lane
+// alone performs the atomic and every active lane gets its old value.  (An
+// atomic issued by every lane with a per-lane value -- v on one lane, 0 on
+// the others -- is compiled into a scan over the active lanes, one lane per
+// iteration, several hundred instructions per call.)  Does not depend on
+// which lanes are active.
+__device__ __forceinline__ uint32_t wave_claim_add(uint32_t *p, uint32_t v)
+{
+    const uint32_t leader = (uint32_t)__builtin_amdgcn_readfirstlane((int)lane_id());
+    uint32_t old = 0;
+    if ((uint32_t)lane_id() == leader) old = atomicAdd(p, v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)old, (int)leader);
+}
+
 }  // namespace arsel
