@@ -260,3 +260,21 @@ def test_run_with_proposal_full_size_sampled(gpu):
     assert np.array_equal(X.cpu().numpy()[ids], xo)
     np.testing.assert_allclose(t.cpu().numpy()[ids], to, rtol=1e-9, atol=0)
     assert np.array_equal(X.cpu().numpy().sum(axis=1), X0.sum(axis=1))
+
+
+@pytest.mark.parametrize("period", [1, 32])
+def test_run_with_the_networks_proposal(gpu, period):
+    """The learned pipeline end to end: the MLP's quantised proposal for the
+    current states (untrained weights, seed 3) drives the run; the oracle
+    replays it on the GPU's Q, so selections, states and times still match."""
+    net = workloads.mass_action_network()
+    X0 = workloads.poisson_counts(N=net.N, R=24, seed=8)
+    X0[:, :64] = 0      # some reactions start inactive and may turn active during the run
+    dn = learned.DeviceNetwork(net)
+    lp = learned.LearnedProposal(net.N, net.M, seed=3)
+    X = torch.from_numpy(X0).cuda()
+    Q, _ = lp.forward(X, dn.propensities(X))
+    Qh = Q.cpu().numpy().view(np.uint32)
+    assert (Qh > 0).any() and (Qh == 0).any()      # zeros where a reaction is inactive
+    qfloor = (1 << (31 - (net.M - 1).bit_length())) // (8 * net.M)
+    _run_both_q(net, X0, Qh, seed=4, step0=3, steps=150, qfloor=qfloor, period=period)
