@@ -278,3 +278,17 @@ def test_run_with_the_networks_proposal(gpu, period):
     assert (Qh > 0).any() and (Qh == 0).any()      # zeros where a reaction is inactive
     qfloor = (1 << (31 - (net.M - 1).bit_length())) // (8 * net.M)
     _run_both_q(net, X0, Qh, seed=4, step0=3, steps=150, qfloor=qfloor, period=period)
+
+
+@pytest.mark.parametrize("period", [1, 64])
+def test_run_invalid_propensities(gpu, period):
+    """A propensity that turns negative during the run (kept by the
+    maintained counts between exact steps) and a NaN rate: -2, as the oracle."""
+    i32 = lambda v: np.array(v, np.int32)
+    X0 = np.tile(np.array([[5, 0, 0]], np.int32), (9, 1))
+    for rate1 in (-1.0, np.nan):
+        net = workloads.Network(N=3, r0=i32([0, 1, 2]), r1=i32([-1, -1, -1]), p0=i32([1, 2, 0]),
+                                p1=i32([-1, -1, -1]), rate=np.array([1.0, rate1, 1.0], np.float32))
+        _run_both(net, X0, seed=2, step0=0, steps=6, period=period)
+        Q = np.full((9, 3), 5, np.uint32)
+        _run_both_q(net, X0, Q, seed=2, step0=0, steps=6, period=period)

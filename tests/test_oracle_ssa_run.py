@@ -179,3 +179,23 @@ def test_bound_mode_resumes_at_period_boundaries(proposal):
     a = oracle.ssa_run(net, X0, seed=4, step0=0, steps=96, threads=8, Q=Q, period=1)
     b = oracle.ssa_run(net, X0, seed=4, step0=0, steps=96, threads=8, Q=Q, period=0)
     assert np.array_equal(a[2], b[2]) and not np.array_equal(a[2], whole[2])
+
+
+def _invalid_rate_net(rate1):
+    """A -> B (rate 1), B -> C (rate rate1), C -> A (rate 1)."""
+    i32 = lambda v: np.array(v, np.int32)
+    return workloads.Network(N=3, r0=i32([0, 1, 2]), r1=i32([-1, -1, -1]), p0=i32([1, 2, 0]),
+                             p1=i32([-1, -1, -1]), rate=np.array([1.0, rate1, 1.0], np.float32))
+
+
+@pytest.mark.parametrize("period", [1, 64])
+def test_invalid_propensity_appearing_mid_run(period):
+    """B -> C has a negative rate: its propensity is -0.0 (valid) while B = 0
+    and negative once A -> B has fired, from then on every step records -2
+    and nothing moves; a NaN rate is invalid from the start."""
+    X0 = np.tile(np.array([[5, 0, 0]], np.int32), (8, 1))
+    x, t, f, _ = oracle.ssa_run(_invalid_rate_net(-1.0), X0, seed=2, step0=0, steps=6, period=period)
+    assert np.all(f[0] == 0) and np.all(f[1:] == -2)
+    assert np.all(x == np.array([4, 1, 0])) and np.all(t > 0)
+    x, t, f, _ = oracle.ssa_run(_invalid_rate_net(np.nan), X0, seed=2, step0=0, steps=4, period=period)
+    assert np.all(f == -2) and np.all(x == X0) and np.all(t == 0)
