@@ -270,19 +270,14 @@ __global__ void k_features(const int32_t *X, int32_t R, int32_t N, int32_t Kp, _
 }
 
 // One wavefront per row: masked softmax of z over alpha_j > 0, then Q.
-// For training (p_grad != null): dz_j = (q_j - p_j) * scale with
+// For training (dz_b / dz_f not null): dz_j = (q_j - p_j) * scale with
 // p_j = alpha_j / sum alpha (FP32), written as BF16 and FP32; the row's
-// cross-entropy -sum p_j log q_j is added to *loss (scaled).
-__global__ void k_softmax_quant(const float *Z, int64_t ldz, const float *alpha, int32_t R,
-                                int32_t M, int32_t L, float *q_out, uint32_t *Q_out,
-                                __bf16 *dz_b, float *dz_f, int64_t lddz, float scale,
-                                float *loss)
+// cross-entropy -sum p_j log q_j goes to *ce_out (the kernel adds the
+// workgroup's rows to the loss, scaled).
+__device__ void softmax_row(const float *z, const float *a, int64_t r, int32_t M, int32_t L,
+                            float *q_out, uint32_t *Q_out, __bf16 *dz_b, float *dz_f,
+                            int64_t lddz, float scale, float *ce_out, int lane)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (r >= R) return;
-    const float *z = Z + r * ldz;
-    const float *a = alpha + r * M;
     float zmax = -INFINITY, asum = 0.0f;
     for (int j = lane; j < M; j += 64) {
         if (a[j] > 0.0f) {
@@ -326,11 +321,39 @@ __global__ void k_softmax_quant(const float *Z, int64_t ldz, const float *alpha,
         if (dz_b) dz_b[r * lddz + j] = (__bf16)0.0f;
         if (dz_f) dz_f[r * lddz + j] = 0.0f;
     }
-    if (loss) {
+    if (ce_out) {
         for (int off = 32; off >= 1; off >>= 1) ce += __shfl_xor(ce, off, 64);
-        if (lane == 0) atomicAdd(loss, ce * scale);
+        if (lane == 0) *ce_out = ce;
     }
 }
+
+constexpr int kSoftmaxWaves = 16;   // rows (wavefronts) per workgroup
+
+__global__ __launch_bounds__(kSoftmaxWaves * 64) void k_softmax_quant(
+    const float *Z, int64_t ldz, const float *alpha, int32_t R, int32_t M, int32_t L, float *q_out,
+    uint32_t *Q_out, __bf16 *dz_b, float *dz_f, int64_t lddz, float scale, float *loss)
+{
+    __shared__ float ce_row[kSoftmaxWaves];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * kSoftmaxWaves + wave;
+    if (r < R)
+        softmax_row(Z + r * ldz, alpha + r * M, r, M, L, q_out, Q_out, dz_b, dz_f, lddz, scale,
+                    loss ? &ce_row[wave] : nullptr, lane);
+    else if (loss && lane == 0)
+        ce_row[wave] = 0.0f;
+    if (loss) {
+        // the workgroup's rows summed in a fixed order, one atomic per workgroup
+        // (one per row put 10^3 same-address atomics in series per training step)
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float acc = 0.0f;
+            for (int w = 0; w < kSoftmaxWaves; ++w) acc += ce_row[w];
+            atomicAdd(loss, acc * scale);
+        }
+    }
+}
+
 
 // Column sums of a [R][ld] FP32 matrix (bias gradients): out[n] = sum_r D[r][n].
 // A workgroup owns 64 columns; its 16 row groups each sum rows g, g+16, ...
@@ -487,7 +510,8 @@ extern "C" int arsel_mlp_forward(arsel_ctx *ctx, const arsel_mlp *net, const int
     Carver cv{(char *)ctx->ws, 0};
     Fwd f;
     if ((rc = forward(ctx, net, X, R, cv, f, s))) return rc;
-    hipLaunchKernelGGL(k_softmax_quant, dim3((R + 3) / 4), dim3(256), 0, s, f.Z, (int64_t)net->Mp,
+    hipLaunchKernelGGL(k_softmax_quant, dim3((R + kSoftmaxWaves - 1) / kSoftmaxWaves),
+                       dim3(kSoftmaxWaves * 64), 0, s, f.Z, (int64_t)net->Mp,
                        alpha, R, net->M, ceil_log2_host(net->M), q_out, Q_out, (__bf16 *)nullptr,
                        (float *)nullptr, (int64_t)0, 0.0f, (float *)nullptr);
     return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
@@ -524,7 +548,8 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
 
     hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, loss, (int64_t)1);
     const float scale = 1.0f / (float)B;
-    hipLaunchKernelGGL(k_softmax_quant, dim3((B + 3) / 4), dim3(256), 0, s, f.Z, (int64_t)n->Mp, alpha,
+    hipLaunchKernelGGL(k_softmax_quant, dim3((B + kSoftmaxWaves - 1) / kSoftmaxWaves),
+                       dim3(kSoftmaxWaves * 64), 0, s, f.Z, (int64_t)n->Mp, alpha,
                        B, n->M, ceil_log2_host(n->M), (float *)nullptr, (uint32_t *)nullptr, dZb, dZf,
                        (int64_t)n->Mp, scale, loss);
     // gradients: grad[0..5] = dW1, db1, dW2, db2, dW3, db3 (FP32, shapes of the masters)
