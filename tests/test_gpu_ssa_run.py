@@ -292,3 +292,32 @@ def test_run_invalid_propensities(gpu, period):
         _run_both(net, X0, seed=2, step0=0, steps=6, period=period)
         Q = np.full((9, 3), 5, np.uint32)
         _run_both_q(net, X0, Q, seed=2, step0=0, steps=6, period=period)
+
+
+def test_run_argument_errors_and_no_ops(gpu):
+    import ctypes
+
+    from paper_1404_0027_amd import arsel
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    dn = learned.DeviceNetwork(net)
+    d, n = dn.deps()
+    X = torch.from_numpy(workloads.poisson_counts(N=64, R=4, seed=1)).cuda()
+    X_before = X.clone()
+    t = torch.zeros(4, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    run = lambda dp, xp, R, steps, tp: arsel.lib().arsel_ssa_run(
+        arsel.context(0), ctypes.byref(dn.c), dp, n.data_ptr(), xp, R, 1, 0, steps, 4096, 64, tp,
+        None, None, st)
+    assert run(d.data_ptr(), X.data_ptr(), 0, 10, t.data_ptr()) == 0        # R = 0: nothing
+    assert run(d.data_ptr(), X.data_ptr(), 4, 0, t.data_ptr()) == 0         # steps = 0: nothing
+    assert run(d.data_ptr(), X.data_ptr(), -1, 10, t.data_ptr()) == -2      # ARSEL_ERR_SIZE
+    assert run(d.data_ptr(), X.data_ptr(), 4, -1, t.data_ptr()) == -2
+    assert run(None, X.data_ptr(), 4, 10, t.data_ptr()) == -1               # ARSEL_ERR_NULL
+    assert run(d.data_ptr(), None, 4, 10, t.data_ptr()) == -1
+    assert run(d.data_ptr(), X.data_ptr(), 4, 10, None) == -1
+    torch.cuda.synchronize()
+    assert torch.equal(X, X_before) and torch.count_nonzero(t) == 0
+    bad = arsel.Network(net.N, net.M, None, None, None, None, None)
+    assert arsel.lib().arsel_ssa_run(arsel.context(0), ctypes.byref(bad), d.data_ptr(),
+                                     n.data_ptr(), X.data_ptr(), 4, 1, 0, 10, 4096, 64,
+                                     t.data_ptr(), None, None, st) == -1
