@@ -258,8 +258,10 @@ static GemmArgs gemm_args(const void *A, int64_t lda, const void *B, int64_t ldb
 __global__ void k_features(const int32_t *X, int32_t R, int32_t N, int32_t Kp, __bf16 *F)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)R * Kp) return;
-    const int64_t r = idx / Kp;
+    const int64_t total = (int64_t)R * Kp;
+    if (idx >= total) return;
+    // 32-bit division while the index fits (a 64-bit one is a long sequence)
+    const int64_t r = total <= 0xFFFFFFFFll ? (int64_t)((uint32_t)idx / (uint32_t)Kp) : idx / Kp;
     const int i = (int)(idx - r * Kp);
     float v = 0.0f;
     if (i < N) {
@@ -273,32 +275,68 @@ __global__ void k_features(const int32_t *X, int32_t R, int32_t N, int32_t Kp, _
 // For training (dz_b / dz_f not null): dz_j = (q_j - p_j) * scale with
 // p_j = alpha_j / sum alpha (FP32), written as BF16 and FP32; the row's
 // cross-entropy -sum p_j log q_j goes to *ce_out (the kernel adds the
-// workgroup's rows to the loss, scaled).
+// workgroup's rows to the loss, scaled).  Rows of up to 64 * PER elements
+// are read once into registers (one exp per element); longer rows loop over
+// global memory (PER = 0).
+__device__ __forceinline__ float wave_sum_f32(float x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ float wave_max_f32(float x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+template <int PER>
 __device__ void softmax_row(const float *z, const float *a, int64_t r, int32_t M, int32_t L,
                             float *q_out, uint32_t *Q_out, __bf16 *dz_b, float *dz_f,
                             int64_t lddz, float scale, float *ce_out, int lane)
 {
+    constexpr int NR = PER > 0 ? PER : 1;
+    float zr[NR], ar[NR];
+    auto zat = [&](int k, int j) { return PER > 0 ? zr[k] : z[j]; };
+    auto aat = [&](int k, int j) { return PER > 0 ? ar[k] : a[j]; };
+    const int iters = PER > 0 ? PER : (M + 63) / 64;
     float zmax = -INFINITY, asum = 0.0f;
-    for (int j = lane; j < M; j += 64) {
-        if (a[j] > 0.0f) {
-            zmax = fmaxf(zmax, z[j]);
-            asum += a[j];
+#pragma unroll
+    for (int k = 0; k < (PER > 0 ? PER : 1); ++k) {
+        if (PER > 0) {
+            const int j = lane + 64 * k;
+            zr[k] = j < M ? z[j] : 0.0f;
+            ar[k] = j < M ? a[j] : 0.0f;
         }
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-        zmax = fmaxf(zmax, __shfl_xor(zmax, off, 64));
-        asum += __shfl_xor(asum, off, 64);
+    for (int k = 0; k < iters; ++k) {
+        const int j = lane + 64 * k;
+        if (j < M && aat(k, j) > 0.0f) {
+            zmax = fmaxf(zmax, zat(k, j));
+            asum += aat(k, j);
+        }
     }
+    zmax = wave_max_f32(zmax);
+    asum = wave_sum_f32(asum);
     float esum = 0.0f;
-    for (int j = lane; j < M; j += 64)
-        if (a[j] > 0.0f) esum += expf(z[j] - zmax);
-    for (int off = 32; off >= 1; off >>= 1) esum += __shfl_xor(esum, off, 64);
+    for (int k = 0; k < iters; ++k) {
+        const int j = lane + 64 * k;
+        const float e = (j < M && aat(k, j) > 0.0f) ? expf(zat(k, j) - zmax) : 0.0f;
+        if (PER > 0) zr[k] = e;            // the row's exponentials replace its logits
+        esum += e;
+    }
+    esum = wave_sum_f32(esum);
     const float qscale = ldexpf(1.0f, 31 - L);
     const float lse = zmax + logf(esum);
     float ce = 0.0f;
-    for (int j = lane; j < M; j += 64) {
-        const bool sup = a[j] > 0.0f;
-        const float q = sup ? expf(z[j] - zmax) / esum : 0.0f;
+    for (int k = 0; k < iters; ++k) {
+        const int j = lane + 64 * k;
+        if (j >= M) break;
+        const bool sup = aat(k, j) > 0.0f;
+        const float e = PER > 0 ? zr[k] : (sup ? expf(z[j] - zmax) : 0.0f);
+        const float q = sup ? e / esum : 0.0f;
         if (q_out) q_out[r * M + j] = q;
         if (Q_out) {
             uint32_t Q = 0;
@@ -309,7 +347,7 @@ __device__ void softmax_row(const float *z, const float *a, int64_t r, int32_t M
             Q_out[r * M + j] = Q;
         }
         if (dz_b || dz_f) {
-            const float p = sup ? a[j] / asum : 0.0f;
+            const float p = sup ? aat(k, j) / asum : 0.0f;
             const float d = (q - p) * scale;
             if (dz_b) dz_b[r * lddz + j] = (__bf16)d;
             if (dz_f) dz_f[r * lddz + j] = d;
@@ -322,12 +360,13 @@ __device__ void softmax_row(const float *z, const float *a, int64_t r, int32_t M
         if (dz_f) dz_f[r * lddz + j] = 0.0f;
     }
     if (ce_out) {
-        for (int off = 32; off >= 1; off >>= 1) ce += __shfl_xor(ce, off, 64);
+        ce = wave_sum_f32(ce);
         if (lane == 0) *ce_out = ce;
     }
 }
 
 constexpr int kSoftmaxWaves = 16;   // rows (wavefronts) per workgroup
+constexpr int kSoftmaxPer = 24;     // register-resident elements per lane (rows up to 1536)
 
 __global__ __launch_bounds__(kSoftmaxWaves * 64) void k_softmax_quant(
     const float *Z, int64_t ldz, const float *alpha, int32_t R, int32_t M, int32_t L, float *q_out,
@@ -337,9 +376,15 @@ __global__ __launch_bounds__(kSoftmaxWaves * 64) void k_softmax_quant(
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t r = (int64_t)blockIdx.x * kSoftmaxWaves + wave;
-    if (r < R)
-        softmax_row(Z + r * ldz, alpha + r * M, r, M, L, q_out, Q_out, dz_b, dz_f, lddz, scale,
-                    loss ? &ce_row[wave] : nullptr, lane);
+    if (r < R) {
+        float *ce = loss ? &ce_row[wave] : nullptr;
+        if (M <= 64 * kSoftmaxPer)
+            softmax_row<kSoftmaxPer>(Z + r * ldz, alpha + r * M, r, M, L, q_out, Q_out, dz_b,
+                                     dz_f, lddz, scale, ce, lane);
+        else
+            softmax_row<0>(Z + r * ldz, alpha + r * M, r, M, L, q_out, Q_out, dz_b, dz_f, lddz,
+                           scale, ce, lane);
+    }
     else if (loss && lane == 0)
         ce_row[wave] = 0.0f;
     if (loss) {
