@@ -254,21 +254,22 @@ static GemmArgs gemm_args(const void *A, int64_t lda, const void *B, int64_t ldb
 // Elementwise and row kernels.
 // ---------------------------------------------------------------------------
 
-// F[r][i] = bf16(log1p(X[r][i])) for i < N, 0 for N <= i < Kp.
+// F[r][i] = bf16(log1p(X[r][i])) for i < N, 0 for N <= i < Kp.  Counts are
+// integers, so 1 + x is exact in FP32 (x < 2^24) and the hardware logarithm
+// (a few ulp) is far inside the BF16 rounding that follows.  Columns across
+// the x dimension, rows strided over the y dimension.
 __global__ void k_features(const int32_t *X, int32_t R, int32_t N, int32_t Kp, __bf16 *F)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)R * Kp;
-    if (idx >= total) return;
-    // 32-bit division while the index fits (a 64-bit one is a long sequence)
-    const int64_t r = total <= 0xFFFFFFFFll ? (int64_t)((uint32_t)idx / (uint32_t)Kp) : idx / Kp;
-    const int i = (int)(idx - r * Kp);
-    float v = 0.0f;
-    if (i < N) {
-        const int32_t x = X[r * N + i];
-        v = log1pf((float)(x > 0 ? x : 0));
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Kp) return;
+    for (int64_t r = blockIdx.y; r < R; r += gridDim.y) {
+        float v = 0.0f;
+        if (i < N) {
+            const int32_t x = X[r * N + i];
+            v = x > 0 ? __logf(1.0f + (float)x) : 0.0f;
+        }
+        F[r * Kp + i] = (__bf16)v;
     }
-    F[idx] = (__bf16)v;
 }
 
 // One wavefront per row: masked softmax of z over alpha_j > 0, then Q.
@@ -510,7 +511,8 @@ static int forward(arsel_ctx *ctx, const arsel_mlp *n, const int32_t *X, int32_t
     f.H2 = cv.take<__bf16>((size_t)R * n->H);
     f.Z = cv.take<float>((size_t)R * n->Mp);
     (void)ctx;
-    hipLaunchKernelGGL(k_features, grid1((int64_t)R * n->Kp), dim3(256), 0, s, X, R, n->N, n->Kp, f.F);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((n->Kp + 255) / 256), (unsigned)std::min(R, 65535)),
+                       dim3(256), 0, s, X, R, n->N, n->Kp, f.F);
     GemmArgs g = gemm_args(f.F, n->Kp, n->W1, n->Kp, R, n->H, n->Kp);
     g.bias = n->b1;
     g.relu = 1;
