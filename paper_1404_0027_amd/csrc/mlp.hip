@@ -29,7 +29,7 @@ typedef float f32x4m __attribute__((ext_vector_type(4)));
 // 32.  Each thread moves one 16-byte chunk (8 BF16) of each operand tile per
 // step; the next step's chunks are loaded into registers while the MFMAs of
 // the current step run.  With grid.z > 1 the K range is split into grid.z
-// slices of kslice (a multiple of 32) and slice z writes its partial product
+// slices of kslice (a multiple of the k step) and slice z writes its partial product
 // to C + z * M * ldc (summed afterwards in slice order); the epilogue then
 // runs in the reduction.  Epilogue: + bias[n], ReLU, zero where
 // mask(m, n) <= 0, FP32 and/or BF16 out.
@@ -39,7 +39,7 @@ struct GemmArgs {
     const __bf16 *B;
     int64_t lda, ldb;
     int32_t M, N, K;
-    int32_t kslice;           // K range per grid.z slice (multiple of 32)
+    int32_t kslice;           // K range per grid.z slice (multiple of the k step)
     int32_t vec_a, vec_b;     // 16-byte chunks allowed (aligned base, ld % 8 == 0)
     const float *bias;        // [N] or null
     const __bf16 *mask;       // [M][ldm] or null
@@ -52,7 +52,7 @@ struct GemmArgs {
 };
 
 constexpr int kGT = 64;      // tile edge
-constexpr int kGK = 32;      // k step
+constexpr int kGK = 64;      // k step (two 32-wide chunks per operand)
 constexpr int kGPad = 8;     // LDS row padding (bf16)
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -95,11 +95,12 @@ struct Chunk {
         v = c.u;
     }
 
-    __device__ __forceinline__ void store(__bf16 (*S)[kGK + kGPad]) const
+    // into columns koff .. koff + 31 of the tile
+    __device__ __forceinline__ void store(__bf16 (*S)[kGK + kGPad], int koff) const
     {
         const int t = threadIdx.x;
         if (KC) {
-            *reinterpret_cast<u32x4 *>(&S[t >> 2][(t & 3) * 8]) = v;
+            *reinterpret_cast<u32x4 *>(&S[t >> 2][koff + (t & 3) * 8]) = v;
         } else {
             union {
                 u32x4 u;
@@ -108,7 +109,7 @@ struct Chunk {
             c.u = v;
             const int kk = t >> 3, rr = (t & 7) * 8;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) S[rr + e][kk] = c.h[e];
+            for (int e = 0; e < 8; ++e) S[rr + e][koff + kk] = c.h[e];
         }
     }
 };
@@ -129,33 +130,45 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4m){0.f, 0.f, 0.f, 0.f};
 
-    Chunk<A_KC> ca;
-    Chunk<B_KC> cb;
-    if (kb < ke) {
-        ca.load(g.A, g.lda, g.M, g.K, m0, kb, g.vec_a);
-        cb.load(g.B, g.ldb, g.N, g.K, n0, kb, g.vec_b);
-    }
-    for (int k0 = kb; k0 < ke; k0 += kGK) {
-        ca.store(sA);
-        cb.store(sB);
-        __syncthreads();
-        if (k0 + kGK < ke) {
-            ca.load(g.A, g.lda, g.M, g.K, m0, k0 + kGK, g.vec_a);
-            cb.load(g.B, g.ldb, g.N, g.K, n0, k0 + kGK, g.vec_b);
+    // the slice's K range, in steps of 64 loaded as two 32-wide chunks per
+    // operand (chunks past ke or K are zero-filled by the loads)
+    const int kend = ke;
+    Chunk<A_KC> ca[2];
+    Chunk<B_KC> cb[2];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int kk = k0 + 32 * h;
+            ca[h].load(g.A, g.lda, g.M, kend, m0, kk, g.vec_a);
+            cb[h].load(g.B, g.ldb, g.N, kend, n0, kk, g.vec_b);
         }
-        const int kq = (lane >> 4) * 8, rl = lane & 15;
-        bf16x8 a[2], b[2];
+    };
+    if (kb < ke) fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += kGK) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-            a[i] = *reinterpret_cast<const bf16x8 *>(&sA[wm + 16 * i + rl][kq]);
+        for (int h = 0; h < 2; ++h) {
+            ca[h].store(sA, 32 * h);
+            cb[h].store(sB, 32 * h);
+        }
+        __syncthreads();
+        if (k0 + kGK < ke) fetch(k0 + kGK);
+        const int rl = lane & 15;
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            b[j] = *reinterpret_cast<const bf16x8 *>(&sB[wn + 16 * j + rl][kq]);
+        for (int h = 0; h < 2; ++h) {
+            const int kq = 32 * h + (lane >> 4) * 8;
+            bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const bf16x8 *>(&sA[wm + 16 * i + rl][kq]);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                b[j] = *reinterpret_cast<const bf16x8 *>(&sB[wn + 16 * j + rl][kq]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
     // D layout: lane holds rows 4*(lane/16) + r, column lane % 16 of each 16 x 16 block.
