@@ -77,10 +77,14 @@ class DeviceNetwork:
             qfloor: int = 1, period: int = 1):
         """Full SSA run in place on X [R, N] (int32) and t [R] (float64);
         with Q ([R, ldq] int32/uint32 proposal, ldq >= M) the steps select
-        with the proposal Q' = max(Q, qfloor, 1).  period: envelopes exact at
-        the first step and at steps s with s mod period = 0, maintained from
-        the changed propensities between.  Returns (fired [steps, R] or None,
-        times [steps, R] or None)."""
+        with the proposal Q' = max(Q, qfloor, 1).  Pass qfloor on the scale of
+        Q: about sum(Q) / (8 M) (for this module's network output,
+        2^(31 - ceil(log2 M)) // (8 M)); with 1, a reaction inactive when Q was
+        computed that turns active weighs 1 against sum(Q) and can push every
+        step into the fallback.  period: envelopes exact at the first step and
+        at steps s with s mod period = 0, maintained from the changed
+        propensities between (64 is a good choice; 1 is exact every step).
+        Returns (fired [steps, R] or None, times [steps, R] or None)."""
         R = X.shape[0]
         arsel._need(X, torch.int32, R * self.N, "X", self.device)
         arsel._need(t, torch.float64, R, "t", self.device)
