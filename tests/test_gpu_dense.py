@@ -224,3 +224,17 @@ def test_sensitivity_analysis_shape_sampled(gpu):
     assert np.array_equal(a0.cpu().numpy()[ids].view(np.uint32), oa.view(np.uint32))
     del a
     torch.cuda.empty_cache()
+
+
+def test_index_only_bench_configuration(gpu):
+    """The timed configuration writes indices only (no alpha_0, no trial
+    counts): R=4096 x M=1029 SoA, checked against the oracle's indices."""
+    M, K = 1029, 4096
+    buf = workloads.lognormal_soa(M=M, K=K, seed=2, buffers=2)
+    dev = torch.from_numpy(buf).cuda()
+    idx = torch.empty(K, dtype=torch.int32, device="cuda")
+    for b, step in ((0, 7), (1, 500)):
+        arsel.select(dev[b], M, K, K, SOA, seed=1, step=step, index=idx)
+        torch.cuda.synchronize()
+        oi, _, _ = oracle.select_uniform(buf[b], M, K, K, SOA, seed=1, step=step, threads=8)
+        assert np.array_equal(idx.cpu().numpy(), oi), (b, step)

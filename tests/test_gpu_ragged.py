@@ -154,3 +154,22 @@ def test_autotuner_picks_a_valid_schedule_and_results_hold(gpu, restore_schedule
     # cached: the second call does not search
     res2 = autotune.tune_ragged(a, off, rb.offsets, candidates=cands, reps=2)
     assert res2.schedule == res.schedule and res2.table == []
+
+
+def test_ragged_index_only_bench_configuration(gpu, restore_schedule):
+    """The timed configuration (10^4 instances, host sizes, indices only, the
+    autotuned schedule) against the oracle on sampled instances."""
+    from paper_1404_0027_amd import autotune
+
+    rb = workloads.ragged_mix(K=10000, seed=3)
+    a = torch.from_numpy(rb.alpha).cuda()
+    off = torch.from_numpy(rb.offsets).cuda()
+    autotune.tune_ragged(a, off, rb.offsets, reps=2, use_cache=False)
+    idx = torch.empty(rb.K, dtype=torch.int32, device="cuda")
+    rng = np.random.default_rng(5)
+    ids = np.unique(np.r_[rng.choice(rb.K, size=300, replace=False), np.argsort(rb.sizes())[-10:]])
+    for step in (2, 3):
+        arsel.select_ragged(a, off, seed=1, step=step, host_offsets=rb.offsets, index=idx)
+        torch.cuda.synchronize()
+        oi, _, _ = oracle.select_ragged(rb.alpha, rb.offsets, seed=1, step=step, ids=ids, threads=8)
+        assert np.array_equal(idx.cpu().numpy()[ids], oi), step
