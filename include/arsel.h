@@ -130,6 +130,12 @@ int arsel_set_trial_lanes(arsel_ctx *ctx, int32_t lanes);
  * work is taken in index order with one schedule.  M_k == 0 reports -1.
  * Results are bit-identical to arsel_select on each instance with instance
  * id k, whatever the schedule.
+ * The context holds this call's work lists and counters: calls on one context
+ * must not overlap (issue them on one stream).  A call whose host_sizes and
+ * schedule split equal the previous host-sized call's reuses the lists already
+ * on the device and launches one kernel; otherwise the lists are rebuilt and
+ * copied through pinned memory.  A graph that captures this call reads the
+ * lists the context holds when it is replayed.
  */
 int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offsets,
                         int32_t K, const int64_t *host_sizes, uint64_t seed, uint64_t step,

@@ -49,7 +49,10 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
         tab[2 * (i - kLnTabLo)] = log((double)i / 128.0);
         tab[2 * (i - kLnTabLo) + 1] = 128.0 / (double)i;
     }
+    c->order_split = -1;
+    c->order_blocks = c->order_waves = 0;
     if (hipMalloc((void **)&c->queue, 256) != hipSuccess ||
+        hipMemset(c->queue, 0, 256) != hipSuccess ||
         hipMalloc((void **)&c->ln_tab, sizeof(tab)) != hipSuccess ||
         hipMemcpy(c->ln_tab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess) {
         if (c->queue) (void)hipFree(c->queue);

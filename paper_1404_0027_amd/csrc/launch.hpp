@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "../../include/arsel.h"
 
@@ -17,9 +18,13 @@ struct arsel_ctx {
     int dense_waves;          // wavefronts per dense workgroup (4, 8, 16; 0: automatic)
     int trial_lanes;          // lanes per instance of the broadcast kernel (0: automatic)
     arsel_schedule sched;     // ragged schedule
-    uint32_t *queue;          // device counters of the persistent ragged kernel (4 x u32)
+    uint32_t *queue;          // device counters of the persistent ragged kernel, zero
+                              // between calls (the kernel's last workgroup clears them)
     int32_t *order;           // device work lists of the ragged kernel, grown on demand
     size_t order_bytes;
+    std::vector<int64_t> order_sizes;   // host sizes the work lists were built from,
+    int32_t order_split;                // for this wave_max_m (-1: lists not reusable)
+    uint32_t order_blocks, order_waves; // their lengths
     int32_t *staging;         // pinned host staging of the work lists
     size_t staging_bytes;
     hipEvent_t staging_event; // completion of the last staging copy

@@ -26,7 +26,8 @@ struct RaggedArgs {
     const int32_t *list_wave;    // instance ids of the wavefront list
     const uint32_t *counts;      // device list lengths (device-built lists), or null
     uint32_t n_block, n_wave;    // host list lengths (host-built lists)
-    uint32_t *queue;             // [0] workgroup list cursor, [1] wavefront list cursor
+    uint32_t *queue;             // [0] workgroup list cursor, [1] wavefront list cursor,
+                                 // [2], [3] device list lengths, [4] finished workgroups
     int32_t *index;
     float *alpha0;
     uint32_t *trials;
@@ -35,11 +36,6 @@ struct RaggedArgs {
     int32_t lds_max_m;
     int32_t wave_max_m;
 };
-
-__global__ void k_ragged_reset(uint32_t *queue)
-{
-    if (threadIdx.x < 4) queue[threadIdx.x] = 0;
-}
 
 // Device-side split of the instances into the two lists (order arbitrary).
 __global__ void k_ragged_classify(const int64_t *offsets, int32_t K, int32_t wave_max_m,
@@ -157,6 +153,17 @@ __global__ __launch_bounds__(NW * 64) void k_select_ragged(RaggedArgs a)
         }
         if (lane == 0) ragged_write(a, k, o);
     }
+
+    // The last workgroup to finish clears the counters for the next call
+    // (every other workgroup's list claims are done by then).
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&a.queue[4], 1u) == gridDim.x - 1) {
+            __threadfence();
+            for (int c = 0; c < 5; ++c) a.queue[c] = 0;
+        }
+    }
 }
 
 template <int NW>
@@ -200,7 +207,9 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
     if (lds > ctx->lds_per_block - 2048) return ARSEL_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
 
+    const int32_t *held = ctx->order;
     rc = grow((void **)&ctx->order, &ctx->order_bytes, 2 * (size_t)K * sizeof(int32_t));
+    if (rc || ctx->order != held) ctx->order_split = -1;
     if (rc) return rc;
 
     RaggedArgs a;
@@ -218,52 +227,65 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
     a.lds_max_m = sc.lds_max_m;
     a.wave_max_m = sc.wave_max_m;
 
-    hipLaunchKernelGGL(k_ragged_reset, dim3(1), dim3(64), 0, s, ctx->queue);
+    // The counters start at zero: cleared at creation and by the end of every
+    // launch of the kernel.
     if (host_sizes) {
-        // Longest first within each list; the lists go to the device through a
-        // pinned staging buffer (reused once the previous copy has finished).
-        // Counting sort on floor(log2 M) (O(K)): sizes within a factor 2 keep
-        // their order, larger buckets first.
-        auto bucket = [&](int32_t k) {
-            const int64_t m = host_sizes[k];
-            return m <= 1 ? 0 : 63 - __builtin_clzll((unsigned long long)m);
-        };
-        size_t nb[64] = {0};
-        for (int32_t k = 0; k < K; ++k) ++nb[bucket(k)];
-        size_t start[64];
-        size_t acc = 0;
-        for (int b = 63; b >= 0; --b) {
-            start[b] = acc;
-            acc += nb[b];
+        // The lists depend only on the sizes and the split: a call with the
+        // sizes and split of the lists already on the device reuses them.
+        const bool same = ctx->order_split == sc.wave_max_m && ctx->order_sizes.size() == (size_t)K &&
+                          std::equal(host_sizes, host_sizes + K, ctx->order_sizes.begin());
+        if (!same) {
+            ctx->order_split = -1;
+            // Longest first within each list; the lists go to the device through a
+            // pinned staging buffer (reused once the previous copy has finished).
+            // Counting sort on floor(log2 M) (O(K)): sizes within a factor 2 keep
+            // their order, larger buckets first.
+            auto bucket = [&](int32_t k) {
+                const int64_t m = host_sizes[k];
+                return m <= 1 ? 0 : 63 - __builtin_clzll((unsigned long long)m);
+            };
+            size_t nb[64] = {0};
+            for (int32_t k = 0; k < K; ++k) ++nb[bucket(k)];
+            size_t start[64];
+            size_t acc = 0;
+            for (int b = 63; b >= 0; --b) {
+                start[b] = acc;
+                acc += nb[b];
+            }
+            std::vector<int32_t> order(K);
+            for (int32_t k = 0; k < K; ++k) order[start[bucket(k)]++] = k;
+            std::vector<int32_t> blk, wav;
+            blk.reserve(K);
+            wav.reserve(K);
+            for (int32_t k : order) (host_sizes[k] > sc.wave_max_m ? blk : wav).push_back(k);
+            const size_t bytes = 2 * (size_t)K * sizeof(int32_t);
+            if (ctx->staging_event && hipEventSynchronize(ctx->staging_event) != hipSuccess)
+                return ARSEL_ERR_HIP;
+            if (ctx->staging_bytes < bytes) {
+                if (ctx->staging && hipHostFree(ctx->staging) != hipSuccess) return ARSEL_ERR_HIP;
+                ctx->staging = nullptr;
+                ctx->staging_bytes = 0;
+                if (hipHostMalloc((void **)&ctx->staging, bytes, hipHostMallocDefault) != hipSuccess)
+                    return ARSEL_ERR_ALLOC;
+                ctx->staging_bytes = bytes;
+            }
+            std::copy(blk.begin(), blk.end(), ctx->staging);
+            std::copy(wav.begin(), wav.end(), ctx->staging + K);
+            if (hipMemcpyAsync(ctx->order, ctx->staging, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+                return ARSEL_ERR_HIP;
+            if (!ctx->staging_event && hipEventCreateWithFlags(&ctx->staging_event, hipEventDisableTiming) != hipSuccess)
+                return ARSEL_ERR_HIP;
+            if (hipEventRecord(ctx->staging_event, s) != hipSuccess) return ARSEL_ERR_HIP;
+            ctx->order_sizes.assign(host_sizes, host_sizes + K);
+            ctx->order_blocks = (uint32_t)blk.size();
+            ctx->order_waves = (uint32_t)wav.size();
+            ctx->order_split = sc.wave_max_m;
         }
-        std::vector<int32_t> order(K);
-        for (int32_t k = 0; k < K; ++k) order[start[bucket(k)]++] = k;
-        std::vector<int32_t> blk, wav;
-        blk.reserve(K);
-        wav.reserve(K);
-        for (int32_t k : order) (host_sizes[k] > sc.wave_max_m ? blk : wav).push_back(k);
-        const size_t bytes = 2 * (size_t)K * sizeof(int32_t);
-        if (ctx->staging_event && hipEventSynchronize(ctx->staging_event) != hipSuccess)
-            return ARSEL_ERR_HIP;
-        if (ctx->staging_bytes < bytes) {
-            if (ctx->staging && hipHostFree(ctx->staging) != hipSuccess) return ARSEL_ERR_HIP;
-            ctx->staging = nullptr;
-            ctx->staging_bytes = 0;
-            if (hipHostMalloc((void **)&ctx->staging, bytes, hipHostMallocDefault) != hipSuccess)
-                return ARSEL_ERR_ALLOC;
-            ctx->staging_bytes = bytes;
-        }
-        std::copy(blk.begin(), blk.end(), ctx->staging);
-        std::copy(wav.begin(), wav.end(), ctx->staging + K);
-        if (hipMemcpyAsync(ctx->order, ctx->staging, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-            return ARSEL_ERR_HIP;
-        if (!ctx->staging_event && hipEventCreateWithFlags(&ctx->staging_event, hipEventDisableTiming) != hipSuccess)
-            return ARSEL_ERR_HIP;
-        if (hipEventRecord(ctx->staging_event, s) != hipSuccess) return ARSEL_ERR_HIP;
         a.counts = nullptr;
-        a.n_block = (uint32_t)blk.size();
-        a.n_wave = (uint32_t)wav.size();
+        a.n_block = ctx->order_blocks;
+        a.n_wave = ctx->order_waves;
     } else {
+        ctx->order_split = -1;
         hipLaunchKernelGGL(k_ragged_classify, dim3((K + 255) / 256), dim3(256), 0, s, offsets, K,
                            sc.wave_max_m, ctx->order, ctx->order + K, ctx->queue + 2);
         a.counts = ctx->queue + 2;

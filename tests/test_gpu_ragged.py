@@ -173,3 +173,41 @@ def test_ragged_index_only_bench_configuration(gpu, restore_schedule):
         torch.cuda.synchronize()
         oi, _, _ = oracle.select_ragged(rb.alpha, rb.offsets, seed=1, step=step, ids=ids, threads=8)
         assert np.array_equal(idx.cpu().numpy()[ids], oi), step
+
+
+def _sized_batch(seed, K=500):
+    r = np.random.default_rng(seed)
+    sizes = np.round(2 ** r.uniform(0, 14, K)).astype(np.int64)
+    offsets = np.zeros(K + 1, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    alpha = r.exponential(1.0, int(offsets[-1])).astype(np.float32)
+    return alpha, offsets
+
+
+def test_ragged_work_lists_reused_only_for_equal_sizes(gpu):
+    """Calls with the same K alternate between sizes, values and the
+    device-built lists: reused lists never serve other sizes."""
+    A, B = _sized_batch(1), _sized_batch(2)
+    A2 = (np.random.default_rng(3).random(A[0].shape[0]).astype(np.float32), A[1])
+    seq = [(A, True), (A, True), (B, True), (A2, True), (A, False), (A, True), (B, False), (B, True)]
+    for n, ((alpha, offsets), host) in enumerate(seq):
+        g, o = _ragged_both(alpha, offsets, seed=3, step=n, host=host)
+        assert_same(g, o, f"call {n} host={host}")
+
+
+def test_ragged_counters_cleared_between_calls(gpu):
+    """Thirty calls in a row on one stream, outputs pre-filled with a sentinel:
+    every call covers every instance (the kernel's last workgroup clears the
+    list counters for the next one)."""
+    alpha, offsets = _sized_batch(4)
+    a = torch.from_numpy(alpha).cuda()
+    off = torch.from_numpy(offsets).cuda()
+    K = offsets.shape[0] - 1
+    oi, _, _ = oracle.select_ragged(alpha, offsets, seed=5, step=9, threads=8)
+    outs = torch.full((30, K), -7, dtype=torch.int32, device="cuda")
+    for n in range(30):
+        arsel.select_ragged(a, off, seed=5, step=9, host_offsets=offsets if n % 3 else None,
+                            index=outs[n])
+    torch.cuda.synchronize()
+    for n in range(30):
+        assert np.array_equal(outs[n].cpu().numpy(), oi), n
