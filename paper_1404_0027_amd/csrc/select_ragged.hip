@@ -11,7 +11,6 @@
 // chosen by the autotuner and never changes the results: every instance
 // gets the same trial stream and rule as arsel_select with instance id k.
 #include <algorithm>
-#include <vector>
 
 #include "launch.hpp"
 #include "select_block.hpp"
@@ -240,24 +239,6 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
             // pinned staging buffer (reused once the previous copy has finished).
             // Counting sort on floor(log2 M) (O(K)): sizes within a factor 2 keep
             // their order, larger buckets first.
-            auto bucket = [&](int32_t k) {
-                const int64_t m = host_sizes[k];
-                return m <= 1 ? 0 : 63 - __builtin_clzll((unsigned long long)m);
-            };
-            size_t nb[64] = {0};
-            for (int32_t k = 0; k < K; ++k) ++nb[bucket(k)];
-            size_t start[64];
-            size_t acc = 0;
-            for (int b = 63; b >= 0; --b) {
-                start[b] = acc;
-                acc += nb[b];
-            }
-            std::vector<int32_t> order(K);
-            for (int32_t k = 0; k < K; ++k) order[start[bucket(k)]++] = k;
-            std::vector<int32_t> blk, wav;
-            blk.reserve(K);
-            wav.reserve(K);
-            for (int32_t k : order) (host_sizes[k] > sc.wave_max_m ? blk : wav).push_back(k);
             const size_t bytes = 2 * (size_t)K * sizeof(int32_t);
             if (ctx->staging_event && hipEventSynchronize(ctx->staging_event) != hipSuccess)
                 return ARSEL_ERR_HIP;
@@ -269,17 +250,38 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
                     return ARSEL_ERR_ALLOC;
                 ctx->staging_bytes = bytes;
             }
-            std::copy(blk.begin(), blk.end(), ctx->staging);
-            std::copy(wav.begin(), wav.end(), ctx->staging + K);
+            auto bucket = [&](int32_t k) {
+                const int64_t m = host_sizes[k];
+                return m <= 1 ? 0 : 63 - __builtin_clzll((unsigned long long)m);
+            };
+            auto large = [&](int32_t k) { return host_sizes[k] > sc.wave_max_m; };
+            size_t nb[2][64] = {};
+            for (int32_t k = 0; k < K; ++k) ++nb[large(k)][bucket(k)];
+            size_t start[2][64];
+            size_t len[2] = {0, 0};
+            for (int l = 0; l < 2; ++l)
+                for (int b = 63; b >= 0; --b) {
+                    start[l][b] = len[l];
+                    len[l] += nb[l][b];
+                }
+            int32_t *list[2] = {ctx->staging + K, ctx->staging};   // wavefront, workgroup
+            for (int32_t k = 0; k < K; ++k) {
+                const int l = large(k);
+                list[l][start[l][bucket(k)]++] = k;
+            }
             if (hipMemcpyAsync(ctx->order, ctx->staging, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
                 return ARSEL_ERR_HIP;
             if (!ctx->staging_event && hipEventCreateWithFlags(&ctx->staging_event, hipEventDisableTiming) != hipSuccess)
                 return ARSEL_ERR_HIP;
             if (hipEventRecord(ctx->staging_event, s) != hipSuccess) return ARSEL_ERR_HIP;
-            ctx->order_sizes.assign(host_sizes, host_sizes + K);
-            ctx->order_blocks = (uint32_t)blk.size();
-            ctx->order_waves = (uint32_t)wav.size();
-            ctx->order_split = sc.wave_max_m;
+            ctx->order_blocks = (uint32_t)len[1];
+            ctx->order_waves = (uint32_t)len[0];
+            try {
+                ctx->order_sizes.assign(host_sizes, host_sizes + K);
+                ctx->order_split = sc.wave_max_m;
+            } catch (...) {
+                ctx->order_sizes.clear();   // the lists stay valid for this call only
+            }
         }
         a.counts = nullptr;
         a.n_block = ctx->order_blocks;
