@@ -235,7 +235,10 @@ def select_ragged(alpha: torch.Tensor, offsets: torch.Tensor, *, seed: int, step
     alpha: float32 CUDA tensor of concatenated instances; offsets: int64 CUDA
     tensor [K+1].  host_offsets: the same offsets as a numpy array (optional);
     when given, they are checked against alpha's size and the per-instance
-    sizes order the work longest first.
+    sizes order the work longest first.  Repeated calls with the same sizes
+    (and schedule) reuse the work lists already on the device: the call is
+    then a single kernel launch.  Calls sharing a device context must run on
+    one stream, since the lists and counters live in the context.
     """
     import numpy as np
 
