@@ -125,17 +125,23 @@ int arsel_set_trial_lanes(arsel_ctx *ctx, int32_t lanes);
  * Uneven batch in one persistent launch: instance k has
  * M_k = offsets[k+1] - offsets[k] reactions at alpha[offsets[k] ..] (AoS).
  * offsets is a DEVICE array of K+1 int64; host_sizes is NULL or a HOST array
- * of the K sizes, used only to order the work longest-first and to choose the
- * per-instance schedule (wave or whole workgroup, LDS staging); when NULL the
- * work is taken in index order with one schedule.  M_k == 0 reports -1.
+ * of the K sizes.  The instances are split into a workgroup list and a
+ * wavefront list (M_k above or up to the schedule's wave_max_m) taken longest
+ * first by power-of-two size class: with host_sizes the lists are built on the
+ * host, otherwise on the device (one extra small kernel per call; for K above
+ * 65536 the device lists are in arbitrary order).  M_k == 0 reports -1.
  * Results are bit-identical to arsel_select on each instance with instance
- * id k, whatever the schedule.
+ * id k, whatever the schedule or order.
  * The context holds this call's work lists and counters: calls on one context
  * must not overlap (issue them on one stream).  A call whose host_sizes and
  * schedule split equal the previous host-sized call's reuses the lists already
  * on the device and launches one kernel; otherwise the lists are rebuilt and
- * copied through pinned memory.  A graph that captures this call reads the
- * lists the context holds when it is replayed.
+ * copied through pinned memory.
+ * Graph capture: a call with host_sizes NULL may be captured (the lists are
+ * built on the device at replay); a call with host_sizes may be captured only
+ * when it reuses the lists (make one eager call with the same sizes and
+ * schedule first; the replay then reads the lists the context holds), and
+ * returns ARSEL_ERR_ARG when it would rebuild them while the stream captures.
  */
 int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offsets,
                         int32_t K, const int64_t *host_sizes, uint64_t seed, uint64_t step,

@@ -13,8 +13,18 @@ With mirror_bf16 the weights, f, h1, h2 and the propagated gradients are
 rounded to bfloat16 (nearest even) where the GPU stores them in that format;
 all arithmetic is float64.  Without it the computation is plain float64
 (used for the finite-difference pin).
+
+Optimizer: Adam (Kingma & Ba, "Adam: a method for stochastic optimization",
+ICLR 2015, Algorithm 1) on float32 master weights, every operation rounded to
+float32 in the order of that algorithm's update rules (adam_step).
+
+Pins (tests/test_oracle_mlp.py): a network small enough to evaluate by hand
+(forward values, loss), central finite differences of the backward pass,
+and closed forms of two Adam steps on scalars.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -92,3 +102,30 @@ def quantise(q, sup, M):
     Q = np.floor(np.asarray(q, np.float64) * 2.0 ** (31 - L))
     Q = np.where(sup, np.maximum(Q, 1.0), 0.0)
     return Q.astype(np.uint64).astype(np.uint32)
+
+
+def adam_step(w, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8):
+    """One Adam update at step t >= 1 (Kingma & Ba 2015, Algorithm 1), in
+    float32 with each operation rounded as written:
+
+        m_t   = beta1 * m_{t-1} + (1 - beta1) * g
+        v_t   = beta2 * v_{t-1} + (1 - beta2) * (g * g)
+        m_hat = m_t / c1,   c1 = 1 - beta1^t
+        v_hat = v_t / c2,   c2 = 1 - beta2^t
+        w_t   = w_{t-1} - (lr * m_hat) / (sqrt(v_hat) + eps)
+
+    The bias corrections c1, c2 are computed in binary64 from the float32
+    betas and rounded once to float32.  Returns (w_t, m_t, v_t) as new
+    float32 arrays; the bfloat16 copy the GPU keeps is bf16_round(w_t)."""
+    f = np.float32
+    w, m, v, g = (np.asarray(x, dtype=np.float32) for x in (w, m, v, g))
+    b1, b2, e, a = f(beta1), f(beta2), f(eps), f(lr)
+    c1 = f(1.0 - math.pow(float(b1), float(t)))
+    c2 = f(1.0 - math.pow(float(b2), float(t)))
+    m_t = b1 * m + (f(1.0) - b1) * g
+    v_t = b2 * v + (f(1.0) - b2) * (g * g)
+    m_hat = m_t / c1
+    v_hat = v_t / c2
+    w_t = w - (a * m_hat) / (np.sqrt(v_hat) + e)
+    return w_t.astype(np.float32), m_t.astype(np.float32), v_t.astype(np.float32)

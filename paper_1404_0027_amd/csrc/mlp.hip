@@ -444,7 +444,11 @@ __global__ __launch_bounds__(1024) void k_colsum(const float *D, int64_t ld, int
     }
 }
 
-// Adam on FP32 master weights (bias-corrected), refreshing the BF16 copy.
+// Adam on FP32 master weights (Kingma & Ba 2015, Algorithm 1: moments, bias
+// corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t, update), refreshing the
+// BF16 copy.  Every operation is a separately rounded FP32 operation in the
+// order of the algorithm's update rules (no contraction; division and
+// square root correctly rounded).
 __global__ void k_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, int64_t n,
                        float lr, float b1, float b2, float eps, float c1, float c2)
 {
@@ -452,7 +456,7 @@ __global__ void k_adam(float *w, const float *g, float *m, float *v, __bf16 *wb,
     if (i >= n) return;
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * (gi * gi);
     m[i] = mi;
     v[i] = vi;
     const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -648,7 +652,9 @@ extern "C" int arsel_mlp_train_step(arsel_ctx *ctx, const arsel_mlp_train *tr, c
     const int64_t sizes[6] = {(int64_t)n->H * n->Kp, n->H, (int64_t)n->H * n->H, n->H,
                               (int64_t)n->Mp * n->H, n->Mp};
     __bf16 *copies[6] = {(__bf16 *)n->W1, nullptr, (__bf16 *)n->W2, nullptr, (__bf16 *)n->W3, nullptr};
-    const float c1 = 1.0f - powf(tr->beta1, (float)t), c2 = 1.0f - powf(tr->beta2, (float)t);
+    // bias corrections: binary64 power of the FP32 betas, rounded once to FP32
+    const float c1 = (float)(1.0 - pow((double)tr->beta1, (double)t));
+    const float c2 = (float)(1.0 - pow((double)tr->beta2, (double)t));
     for (int i = 0; i < 6; ++i)
         hipLaunchKernelGGL(k_adam, grid1(sizes[i]), dim3(256), 0, s, tr->master[i], tr->grad[i], tr->m[i],
                            tr->v[i], copies[i], sizes[i], lr, tr->beta1, tr->beta2, tr->eps, c1, c2);

@@ -6,8 +6,9 @@
 // gathered from global memory right after the streaming pass that computes
 // the maximum), small ones by a single wavefront.  Persistent workgroups
 // take items from the two lists through atomic counters, the large list
-// first; with host-side sizes both lists are ordered longest first (by
-// power-of-two size class).  The schedule (wave_max_m, waves per workgroup, lds_max_m, workgroups per CU) is
+// first; both lists are ordered longest first by power-of-two size class (on
+// the host when the caller passes the sizes, else by a one-workgroup counting
+// sort on the device).  The schedule (wave_max_m, waves per workgroup, lds_max_m, workgroups per CU) is
 // chosen by the autotuner and never changes the results: every instance
 // gets the same trial stream and rule as arsel_select with instance id k.
 #include <algorithm>
@@ -36,7 +37,66 @@ struct RaggedArgs {
     int32_t wave_max_m;
 };
 
-// Device-side split of the instances into the two lists (order arbitrary).
+// Size class of an instance: floor(log2 M) (0 for M <= 1, negative sizes included).
+__device__ __forceinline__ int size_class(int64_t m)
+{
+    return m <= 1 ? 0 : 63 - __clzll((long long)m);
+}
+
+// Device-side split of the instances into the two lists, ordered longest first
+// by size class (a counting sort in one workgroup), for batches of at most
+// kOrderMaxK instances.  The kernel also sets the counters of the launch that
+// follows: both cursors and the finished-workgroup count to zero, the list
+// lengths to the counts.  It reads nothing the previous call left, so a call
+// that stopped with an error after enqueuing it leaves no state behind.
+constexpr int32_t kOrderMaxK = 1 << 16;
+constexpr int kOrderThreads = 1024;
+
+__global__ __launch_bounds__(kOrderThreads) void k_ragged_order(const int64_t *offsets, int32_t K,
+                                                                int32_t wave_max_m,
+                                                                int32_t *list_block,
+                                                                int32_t *list_wave, uint32_t *queue)
+{
+    __shared__ uint32_t cnt[2][64];
+    __shared__ uint32_t pos[2][64];
+    const int tid = threadIdx.x;
+    if (tid < 128) cnt[tid >> 6][tid & 63] = 0;
+    __syncthreads();
+    for (int k = tid; k < K; k += kOrderThreads) {
+        const int64_t m = offsets[k + 1] - offsets[k];
+        atomicAdd(&cnt[m > wave_max_m][size_class(m)], 1u);
+    }
+    __syncthreads();
+    if (tid < 2) {
+        uint32_t run = 0;
+        for (int b = 63; b >= 0; --b) {
+            pos[tid][b] = run;
+            run += cnt[tid][b];
+        }
+        queue[2 + (tid == 0)] = run;      // queue[2]: workgroup list, queue[3]: wavefront list
+        if (tid == 0) {
+            queue[0] = 0;
+            queue[1] = 0;
+            queue[4] = 0;
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < K; k += kOrderThreads) {
+        const int64_t m = offsets[k + 1] - offsets[k];
+        const int l = m > wave_max_m;
+        const uint32_t p = atomicAdd(&pos[l][size_class(m)], 1u);
+        (l ? list_block : list_wave)[p] = k;
+    }
+}
+
+// Counters of the launch that follows set to zero (larger device-built batches).
+__global__ void k_ragged_reset(uint32_t *queue)
+{
+    if (threadIdx.x < 5) queue[threadIdx.x] = 0;
+}
+
+// Device-side split of the instances into the two lists (order arbitrary);
+// the counters start at zero (k_ragged_reset runs first).
 __global__ void k_ragged_classify(const int64_t *offsets, int32_t K, int32_t wave_max_m,
                                   int32_t *list_block, int32_t *list_wave, uint32_t *counts)
 {
@@ -47,6 +107,23 @@ __global__ void k_ragged_classify(const int64_t *offsets, int32_t K, int32_t wav
         list_block[atomicAdd(&counts[0], 1u)] = k;
     else
         list_wave[atomicAdd(&counts[1], 1u)] = k;
+}
+
+// Device-built work lists and counters for a launch of k_select_ragged.
+static int build_lists_on_device(const int64_t *offsets, int32_t K, int32_t wave_max_m,
+                                 int32_t *list_block, int32_t *list_wave, uint32_t *queue,
+                                 hipStream_t s)
+{
+    if (K <= kOrderMaxK) {
+        hipLaunchKernelGGL(k_ragged_order, dim3(1), dim3(kOrderThreads), 0, s, offsets, K,
+                           wave_max_m, list_block, list_wave, queue);
+    } else {
+        hipLaunchKernelGGL(k_ragged_reset, dim3(1), dim3(64), 0, s, queue);
+        if (hipGetLastError() != hipSuccess) return ARSEL_ERR_HIP;
+        hipLaunchKernelGGL(k_ragged_classify, dim3((K + 255) / 256), dim3(256), 0, s, offsets, K,
+                           wave_max_m, list_block, list_wave, queue + 2);
+    }
+    return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
 }
 
 __device__ __forceinline__ void ragged_write(const RaggedArgs &a, int k, const Outcome &o)
@@ -200,6 +277,7 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
     if (!alpha || !offsets || !index) return ARSEL_ERR_NULL;
     int rc = ctx_activate(ctx);
     if (rc) return rc;
+    (void)hipGetLastError();   // a stale error of earlier work is not this call's
     const arsel_schedule &sc = ctx->sched;
     const int nw = sc.block_waves;
     const size_t lds = std::max<size_t>((size_t)sc.lds_max_m, (size_t)nw * sc.wave_max_m) * sizeof(float);
@@ -226,14 +304,22 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
     a.lds_max_m = sc.lds_max_m;
     a.wave_max_m = sc.wave_max_m;
 
-    // The counters start at zero: cleared at creation and by the end of every
-    // launch of the kernel.
+    // Host-built lists: the counters are zero, cleared at creation and by the
+    // last workgroup of every launch of the kernel (a call that returns an
+    // error launches no kernel that touches them).  Device-built lists: the
+    // ordering kernel sets the counters itself.
     if (host_sizes) {
         // The lists depend only on the sizes and the split: a call with the
         // sizes and split of the lists already on the device reuses them.
         const bool same = ctx->order_split == sc.wave_max_m && ctx->order_sizes.size() == (size_t)K &&
                           std::equal(host_sizes, host_sizes + K, ctx->order_sizes.begin());
         if (!same) {
+            // Rebuilding copies the lists from host memory, which a captured
+            // graph would replay from a buffer later calls overwrite: under
+            // capture only calls that reuse the lists are accepted.
+            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(s, &cap) != hipSuccess) return ARSEL_ERR_HIP;
+            if (cap != hipStreamCaptureStatusNone) return ARSEL_ERR_ARG;
             ctx->order_split = -1;
             // Longest first within each list; the lists go to the device through a
             // pinned staging buffer (reused once the previous copy has finished).
@@ -288,12 +374,12 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
         a.n_wave = ctx->order_waves;
     } else {
         ctx->order_split = -1;
-        hipLaunchKernelGGL(k_ragged_classify, dim3((K + 255) / 256), dim3(256), 0, s, offsets, K,
-                           sc.wave_max_m, ctx->order, ctx->order + K, ctx->queue + 2);
+        if ((rc = build_lists_on_device(offsets, K, sc.wave_max_m, ctx->order, ctx->order + K,
+                                        ctx->queue, s)))
+            return rc;
         a.counts = ctx->queue + 2;
         a.n_block = a.n_wave = 0;
     }
-    if (hipGetLastError() != hipSuccess) return ARSEL_ERR_HIP;
     switch (nw) {
     case 4: return launch_ragged<4>(ctx, a, lds, s);
     case 8: return launch_ragged<8>(ctx, a, lds, s);

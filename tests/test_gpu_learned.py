@@ -4,9 +4,13 @@
   values;
 * mass-action propensities and the SSA jump chain: bit-exact;
 * MLP forward: ||q_gpu - q_cpu|| / ||q_cpu|| <= 1e-2 with the same BF16
-  weights and inputs; Q exactly the quantisation of the GPU's q;
+  weights and inputs, also per row (relative L1) and per element above 1e-4;
+  Q exactly the quantisation of the GPU's q;
 * proposal selection: bit-exact against the oracle fed the GPU's Q;
-* gradients of one training step within 2e-2 (norm-wise) of the CPU backward;
+* gradients of one training step within 2e-2 of the CPU backward, norm-wise
+  and element by element against each tensor's scale;
+* the Adam step (lr > 0, t = 1 and 2): masters, moments and BF16 copies
+  bit-exact against the oracle's float32 Adam fed the GPU's gradients;
 * training raises the per-trial acceptance over uniform AR; the learned
   selections follow alpha_j / alpha_0 (chi-square against the exact law);
 * checkpoint / resume reproduces the weights bit for bit.
@@ -100,6 +104,14 @@ def test_mlp_forward_matches_cpu(net_and_data):
     fw = omlp.forward(_params_np(lp), Xs.cpu().numpy(), As.cpu().numpy(), net.N, net.M)
     qg = q.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(qg - fw["q"]) <= 1e-2 * np.linalg.norm(fw["q"])
+    # row by row: relative L1 error of every state's q (each row sums to 1)
+    row_err = np.abs(qg - fw["q"]).sum(axis=1) / np.abs(fw["q"]).sum(axis=1)
+    assert row_err.max() <= 1e-2, row_err.max()
+    # and element by element, with an absolute floor for the tiny entries
+    err = np.abs(qg - fw["q"])
+    print(f"q: max row L1 {row_err.max():.3e}, max element error / (q + 1e-5) "
+          f"{(err / (fw['q'] + 1e-5)).max():.3e}")
+    assert np.all(err <= 1e-2 * fw["q"] + 1e-5)
     L = laws.ceil_log2(net.M)
     sup = As.cpu().numpy() > 0
     Qref = np.where(sup, np.maximum(np.floor(q.cpu().numpy() * np.float32(2.0 ** (31 - L))), 1), 0)
@@ -149,9 +161,52 @@ def test_gradients_match_cpu(net_and_data):
     for i, (g, r) in enumerate(zip(lp.grad, ref_g)):
         g = g.cpu().numpy().astype(np.float64)
         assert np.linalg.norm(g - r) <= 2e-2 * np.linalg.norm(r) + 1e-12, i
+        # element by element against the tensor's scale: a wrong row or column
+        # (a missing bias entry, a transposed operand) cannot hide in the norm
+        err = np.abs(g - r)
+        assert err.max() <= 2e-2 * np.abs(r).max() + 1e-12, (i, err.max(), np.abs(r).max())
+        if r.ndim == 2:
+            # per row and per column of the weight gradient, against that
+            # row's or column's own scale
+            for axis in (0, 1):
+                scale = np.abs(r).max(axis=axis)
+                worst = (err.max(axis=axis) / (scale + 1e-3 * np.abs(r).max())).max()
+                print(f"grad {i} axis {axis}: worst error / (scale + floor) {worst:.3e}")
+                assert worst <= 1e-1, (i, axis, worst)
     # lr = 0 leaves the weights unchanged
     for t, p in zip(lp.master, params):
         assert np.array_equal(t.cpu().numpy().astype(np.float64), p)
+
+
+@pytest.mark.parametrize("lr", [1e-3, 3e-2])
+def test_adam_step_matches_oracle(net_and_data, lr):
+    """Two training steps with lr > 0 (t = 1 and t = 2): the FP32 masters and
+    both Adam moments equal the oracle's float32 Adam fed the GPU's own
+    gradients, bit for bit, and the BF16 copies are the masters rounded to
+    nearest even."""
+    net, dn, X, alpha = net_and_data
+    lp = learned.LearnedProposal(net.N, net.M, seed=13)
+    B = 512
+    for t in (1, 2):
+        w0 = [x.cpu().numpy().copy() for x in lp.master]
+        m0 = [x.cpu().numpy().copy() for x in lp.m]
+        v0 = [x.cpu().numpy().copy() for x in lp.v]
+        lp.train_step(X[(t - 1) * B:t * B].contiguous(), alpha[(t - 1) * B:t * B].contiguous(),
+                      lr=lr)
+        torch.cuda.synchronize()
+        assert lp.t == t
+        for i in range(6):
+            g = lp.grad[i].cpu().numpy()
+            w1, m1, v1 = omlp.adam_step(w0[i], m0[i], v0[i], g, t, lr)
+            for name, got, want in (("w", lp.master[i], w1), ("m", lp.m[i], m1),
+                                    ("v", lp.v[i], v1)):
+                got = got.cpu().numpy()
+                diff = got.view(np.uint32) != want.view(np.uint32)
+                assert not diff.any(), (t, i, name, int(diff.sum()), got[diff][:4], want[diff][:4])
+        for wb, i in zip(lp.Wb, (0, 2, 4)):
+            got = wb.cpu().view(torch.int16).numpy().astype(np.uint16)
+            want = (omlp.bf16_round(lp.master[i].cpu().numpy()).view(np.uint32) >> 16).astype(np.uint16)
+            assert np.array_equal(got, want), (t, i)
 
 
 def _acceptance(trials):

@@ -97,16 +97,14 @@ def test_ragged_edge_instances(gpu):
     assert g[0][6] == -1 and g[0][10] == -1 and g[0][9] == 10
 
 
-def test_ragged_full_size_sampled(gpu):
+def test_ragged_full_size(gpu):
     """10^4 instances, M log-uniform in [64, 65536] (about 9.4e7 propensities):
-    the whole batch in one launch, 400 sampled instances checked against the
-    oracle (instance ids preserved)."""
+    the whole batch in one launch, every instance checked against the oracle
+    (indices, alpha_0 and trial counts), with and without host sizes."""
     rb = workloads.ragged_mix(K=10000, seed=3)
-    rng = np.random.default_rng(0)
-    ids = np.sort(rng.choice(rb.K, size=400, replace=False))
-    ids = np.unique(np.r_[ids, np.argsort(rb.sizes())[-20:]])   # include the largest
-    g, o = _ragged_both(rb.alpha, rb.offsets, seed=1, step=0, ids=ids)
-    assert_same(g, o, "ragged full size (sampled)")
+    for host in (True, False):
+        g, o = _ragged_both(rb.alpha, rb.offsets, seed=1, step=0, host=host)
+        assert_same(g, o, f"ragged full size host={host}")
 
 
 def test_ragged_matches_dense(gpu):
@@ -158,7 +156,8 @@ def test_autotuner_picks_a_valid_schedule_and_results_hold(gpu, restore_schedule
 
 def test_ragged_index_only_bench_configuration(gpu, restore_schedule):
     """The timed configuration (10^4 instances, host sizes, indices only, the
-    autotuned schedule) against the oracle on sampled instances."""
+    autotuned schedule) against the oracle on every instance, two steps (the
+    second call reuses the device work lists)."""
     from paper_1404_0027_amd import autotune
 
     rb = workloads.ragged_mix(K=10000, seed=3)
@@ -166,13 +165,11 @@ def test_ragged_index_only_bench_configuration(gpu, restore_schedule):
     off = torch.from_numpy(rb.offsets).cuda()
     autotune.tune_ragged(a, off, rb.offsets, reps=2, use_cache=False)
     idx = torch.empty(rb.K, dtype=torch.int32, device="cuda")
-    rng = np.random.default_rng(5)
-    ids = np.unique(np.r_[rng.choice(rb.K, size=300, replace=False), np.argsort(rb.sizes())[-10:]])
     for step in (2, 3):
         arsel.select_ragged(a, off, seed=1, step=step, host_offsets=rb.offsets, index=idx)
         torch.cuda.synchronize()
-        oi, _, _ = oracle.select_ragged(rb.alpha, rb.offsets, seed=1, step=step, ids=ids, threads=8)
-        assert np.array_equal(idx.cpu().numpy()[ids], oi), step
+        oi, _, _ = oracle.select_ragged(rb.alpha, rb.offsets, seed=1, step=step, threads=8)
+        assert np.array_equal(idx.cpu().numpy(), oi), step
 
 
 def _sized_batch(seed, K=500):
@@ -211,3 +208,69 @@ def test_ragged_counters_cleared_between_calls(gpu):
     torch.cuda.synchronize()
     for n in range(30):
         assert np.array_equal(outs[n].cpu().numpy(), oi), n
+
+
+def test_ragged_graph_capture_replays_match_eager(gpu):
+    """Captured calls (one reusing host-built lists, one with device-built
+    lists) replayed several times, with eager calls on other sizes between
+    the replays: every replay equals the eager result; a call that would
+    rebuild host lists during capture is refused."""
+    A, B = _sized_batch(11), _sized_batch(12)
+    a = torch.from_numpy(A[0]).cuda()
+    off = torch.from_numpy(A[1]).cuda()
+    b = torch.from_numpy(B[0]).cuda()
+    offb = torch.from_numpy(B[1]).cuda()
+    K = A[1].shape[0] - 1
+    ref, _, _ = oracle.select_ragged(A[0], A[1], seed=8, step=4, threads=8)
+    arsel.select_ragged(a, off, seed=8, step=4, host_offsets=A[1])       # eager: lists built
+    torch.cuda.synchronize()
+    out_h = torch.full((K,), -7, dtype=torch.int32, device="cuda")
+    out_d = torch.full((K,), -7, dtype=torch.int32, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(g, stream=cap, capture_error_mode="relaxed"):
+            arsel.select_ragged(a, off, seed=8, step=4, host_offsets=A[1], index=out_h)
+            arsel.select_ragged(a, off, seed=8, step=4, index=out_d)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        out_h.fill_(-7)
+        out_d.fill_(-7)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out_h.cpu().numpy(), ref), rep
+        assert np.array_equal(out_d.cpu().numpy(), ref), rep
+        # eager work between replays: another batch, device-built lists
+        ob, _, _ = arsel.select_ragged(b, offb, seed=1, step=rep)
+        torch.cuda.synchronize()
+    # the captured host-list call reads the context's lists: rebuild them for A
+    arsel.select_ragged(a, off, seed=8, step=4, host_offsets=A[1])
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(out_h.cpu().numpy(), ref)
+    # rebuilding host lists under capture is refused
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(cap):
+        with pytest.raises(arsel.ArselError):
+            with torch.cuda.graph(g2, stream=cap, capture_error_mode="relaxed"):
+                arsel.select_ragged(b, offb, seed=1, step=0, host_offsets=B[1])
+    torch.cuda.synchronize()
+    # and the context still works afterwards
+    g_, o_ = _ragged_both(B[0], B[1], seed=2, step=3)
+    assert_same(g_, o_, "after a refused capture")
+
+
+def test_ragged_device_lists_large_batch(gpu):
+    """More than 65536 instances with device-built lists (reset + unordered
+    split) and with host sizes: every instance against the oracle."""
+    r = np.random.default_rng(21)
+    K = 70000
+    sizes = np.round(2 ** r.uniform(0, 9, K)).astype(np.int64)
+    offsets = np.zeros(K + 1, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    alpha = r.exponential(1.0, int(offsets[-1])).astype(np.float32)
+    for host in (False, True, False):
+        g, o = _ragged_both(alpha, offsets, seed=3, step=1, host=host)
+        assert_same(g, o, f"K={K} host={host}")

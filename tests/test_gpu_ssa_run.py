@@ -118,10 +118,20 @@ def test_run_resumes_at_period_boundaries(gpu):
     np.testing.assert_allclose(ta.cpu().numpy(), tb.cpu().numpy(), rtol=1e-10)
 
 
+def _sample_ids(R, n, seed):
+    """n realization ids: half even, half odd (the two halves of a wavefront in
+    the two-realizations-per-wavefront kernel), plus the first and the last."""
+    rng = np.random.default_rng(seed)
+    ev = 2 * rng.choice(R // 2, n // 2, replace=False)
+    od = 2 * rng.choice(R // 2, n // 2, replace=False) + 1
+    return np.unique(np.r_[ev, od, 0, R - 1]).astype(np.uint32)
+
+
 @pytest.mark.parametrize("period", [1, 64])
 def test_run_full_size_sampled(gpu, period):
     """R = 16384 realizations x 10^4 steps of the N=641, M=1029 network in one
-    launch; four realizations replayed by the oracle (instance ids kept)."""
+    launch; 1024 realizations (512 even and 512 odd ids, plus the first and
+    the last) replayed by the oracle (instance ids kept)."""
     net = workloads.mass_action_network()
     R, steps = 16384, 10000
     X0 = workloads.poisson_counts(N=net.N, R=R, seed=5)
@@ -130,8 +140,8 @@ def test_run_full_size_sampled(gpu, period):
     t = torch.zeros(R, dtype=torch.float64, device="cuda")
     dn.run(X, t, seed=7, step0=0, steps=steps, period=period)
     torch.cuda.synchronize()
-    ids = np.array([0, 5001, 12345, R - 1], np.uint32)
-    xo, to, _, _ = oracle.ssa_run(net, X0[ids], seed=7, step0=0, steps=steps, ids=ids, threads=4,
+    ids = _sample_ids(R, 1024, seed=period)
+    xo, to, _, _ = oracle.ssa_run(net, X0[ids], seed=7, step0=0, steps=steps, ids=ids, threads=16,
                                   period=period)
     assert np.array_equal(X.cpu().numpy()[ids], xo)
     np.testing.assert_allclose(t.cpu().numpy()[ids], to, rtol=1e-9, atol=0)
@@ -241,11 +251,12 @@ def test_run_with_proposal_argument_errors(gpu):
 
 def test_run_with_proposal_full_size_sampled(gpu):
     """R = 16384 x 10^4 steps with the proposal shaped on the initial states;
-    four realizations replayed by the oracle (instance ids kept)."""
+    258 realizations (even and odd ids, the first and the last) replayed by
+    the oracle (instance ids kept)."""
     net = workloads.mass_action_network()
     R, steps = 16384, 10000
     X0 = workloads.poisson_counts(N=net.N, R=R, seed=5)
-    ids = np.array([0, 777, 9999, R - 1], np.uint32)
+    ids = _sample_ids(R, 256, seed=9)
     Q = np.zeros((R, net.M), np.uint32)
     Q[ids] = _shaped_q(net, X0[ids])
     Q[np.setdiff1d(np.arange(R), ids)] = 3
@@ -255,7 +266,7 @@ def test_run_with_proposal_full_size_sampled(gpu):
     dn.run(X, t, seed=7, step0=0, steps=steps, Q=torch.from_numpy(Q.view(np.int32)).cuda(),
            qfloor=60, period=64)
     torch.cuda.synchronize()
-    xo, to, _, _ = oracle.ssa_run(net, X0[ids], seed=7, step0=0, steps=steps, ids=ids, threads=4,
+    xo, to, _, _ = oracle.ssa_run(net, X0[ids], seed=7, step0=0, steps=steps, ids=ids, threads=16,
                                   Q=Q[ids], qfloor=60, period=64)
     assert np.array_equal(X.cpu().numpy()[ids], xo)
     np.testing.assert_allclose(t.cpu().numpy()[ids], to, rtol=1e-9, atol=0)
