@@ -128,6 +128,48 @@ def bench_ragged(torch, arsel, workloads, reps: int = 20):
             "note": "includes the host-side longest-first ordering of each call"}
 
 
+def law_pvalue_rows(np, alpha_rows, rows, sel, bins: int = 64, seed: int = 0):
+    """p-value that selections `sel` (index chosen for row rows[i] of
+    alpha_rows [R, M]) follow alpha_j / alpha_0 of their own rows: the
+    randomised probability integral transform F(j-) + V p_j is U(0,1) under
+    that law; chi-square of its histogram over `bins` equal cells."""
+    from scipy.stats import chi2
+
+    a = np.asarray(alpha_rows, np.float64)
+    P = a / a.sum(axis=1, keepdims=True)
+    C = np.cumsum(P, axis=1)
+    rows = np.asarray(rows)
+    sel = np.asarray(sel, np.int64)
+    if np.any(sel < 0):
+        return 0.0
+    hi = C[rows, sel]
+    lo = hi - P[rows, sel]
+    u = lo + np.random.default_rng(seed).random(sel.size) * (hi - lo)
+    h = np.bincount(np.minimum((u * bins).astype(np.int64), bins - 1), minlength=bins)
+    e = sel.size / bins
+    return float(chi2.sf(((h - e) ** 2 / e).sum(), bins - 1))
+
+
+def law_pvalue_counts(np, alpha, counts):
+    """Chi-square p-value of selection counts of one vector against
+    alpha_j / alpha_0 (cells with expectation below 5 merged)."""
+    from scipy.stats import chi2
+
+    p = np.asarray(alpha, np.float64)
+    p = p / p.sum()
+    c = np.asarray(counts, np.float64)
+    n = c.sum()
+    e = n * p
+    keep = e >= 5
+    obs = list(c[keep])
+    exp = list(e[keep])
+    if (~keep).any():
+        obs.append(c[~keep].sum())
+        exp.append(e[~keep].sum())
+    obs, exp = np.asarray(obs), np.asarray(exp)
+    return float(chi2.sf(((obs - exp) ** 2 / exp).sum(), obs.size - 1))
+
+
 def _acceptance(np, trials):
     t = trials.cpu().numpy().view(np.uint32).astype(np.int64)
     ok = (t >= 1) & (t <= 4096)
@@ -209,12 +251,27 @@ def bench_learned(torch, np, arsel, workloads, epochs: int = 8, lr0: float = 2e-
 
     t_f = _timed(torch, full, 50)
 
+    # selection law of the timed launches: 20 steps of each path, every
+    # selection against its own state's alpha_j / alpha_0
+    Ah_np = Ah.cpu().numpy()
+    law = {}
+    for name, call in (("uniform_AR", lambda s: arsel.select(Ah, net.M, Rh, net.M, arsel.AOS,
+                                                             seed=SEED, step=s, index=idx)),
+                       ("learned", lambda s: arsel.select_proposal(Ah, Q, seed=SEED, step=s,
+                                                                   index=idx))):
+        sel = []
+        for s in range(1, 21):
+            call(s)
+            sel.append(idx.cpu().numpy().copy())
+        sel = np.concatenate(sel)
+        law[name] = round(law_pvalue_rows(np, Ah_np, np.tile(np.arange(Rh), 20), sel), 4)
+
     # (b) ensembles from common states: K selections from each of 8 held-out
     # states (the first step of K realizations started from that state)
     K = 1 << 20
     bi = torch.empty(K, dtype=torch.int32, device="cuda")
     bt = torch.empty(K, dtype=torch.int32, device="cuda")
-    rates_u, rates_l, accs_u, accs_l = [], [], [], []
+    rates_u, rates_l, accs_u, accs_l, ens_p = [], [], [], [], []
     for s in range(8):
         a1, q1 = Ah[s].contiguous(), Q[s].contiguous()
         arsel.select(a1, net.M, K, 0, arsel.AOS, seed=SEED, index=bi, trials=bt)
@@ -225,6 +282,9 @@ def bench_learned(torch, np, arsel, workloads, epochs: int = 8, lr0: float = 2e-
                                                                   seed=SEED, step=st, index=bi), 20))
         rates_l.append(K / _timed(torch, lambda st: arsel.select_proposal_broadcast(
             a1, q1, K, seed=SEED, step=st, index=bi), 20))
+        # the last timed launch's K selections against this state's law
+        cnt = torch.bincount(bi.long(), minlength=net.M)[:net.M].cpu().numpy()
+        ens_p.append(law_pvalue_counts(np, a1.cpu().numpy(), cnt))
     ru, rl = float(np.mean(rates_u)), float(np.mean(rates_l))
     return {"workload": "mass-action network N=641, M=1029, counts Poisson(50); MLP "
                         "641->256->256->1029 BF16 on MFMA; held-out states = 4096 fresh "
@@ -239,14 +299,20 @@ def bench_learned(torch, np, arsel, workloads, epochs: int = 8, lr0: float = 2e-
                                          "gain": round(acc_l / acc_u, 2)},
                 "selections_per_s": {"uniform_AR": round(Rh / t_u, 1),
                                      "learned_select_only": round(Rh / t_p, 1),
-                                     "learned_with_MLP_forward": round(Rh / t_f, 1)}},
+                                     "learned_with_MLP_forward": round(Rh / t_f, 1)},
+                "law_chi2_p": dict(law, what="20 launches x 4096 selections per path, each "
+                                   "against its own state's alpha_j / alpha_0 (randomised "
+                                   "PIT, 64 cells)")},
             "ensemble": {
                 "what": f"{K} selections from each of 8 held-out states (alpha, Q staged once; "
                         "trial-bound), automatic trial width for both",
                 "acceptance_per_trial": {"uniform": round(float(np.mean(accs_u)), 5),
                                          "learned": round(float(np.mean(accs_l)), 5)},
                 "selections_per_s": {"uniform_AR": round(ru, 1), "learned": round(rl, 1),
-                                     "speedup": round(rl / ru, 2)}}}, lp
+                                     "speedup": round(rl / ru, 2)},
+                "learned_law_chi2_p": {"per_state": [round(x, 4) for x in ens_p],
+                                       "what": "the last timed learned launch (2^20 selections) "
+                                               "of each state against alpha_j / alpha_0"}}}, lp
 
 
 def bench_ssa(torch, np, arsel, workloads, lp=None, refresh: int = 1000, period: int = 64):
@@ -319,10 +385,13 @@ def bench_ssa(torch, np, arsel, workloads, lp=None, refresh: int = 1000, period:
                 acc["uniform"].append(_acceptance(np, tr))
                 arsel.select_proposal(a, Q, seed=SEED, step=seg, trials=tr)
                 acc["learned"].append(_acceptance(np, tr))
-            dn.run(X, t, seed=SEED, step0=seg, steps=min(refresh, steps - seg), Q=Q, qfloor=qfloor,
-                   period=p)
+            fired, _ = dn.run(X, t, seed=SEED, step0=seg, steps=min(refresh, steps - seg), Q=Q,
+                              qfloor=qfloor, period=p, want_fired=acc is not None)
+            if acc is not None:       # the segment's first step selected from the refresh states
+                acc["law_a"].append(a.cpu().numpy())
+                acc["law_sel"].append(fired[0].cpu().numpy())
 
-    acc = {"uniform": [], "learned": []}
+    acc = {"uniform": [], "learned": [], "law_a": [], "law_sel": []}
     timed(lambda: learned_run(period, acc))                 # (acceptance pass)
     sec_l = {p: timed(lambda: learned_run(p)) for p in (1, period)}
     out["with_learned_proposal"] = {
@@ -335,6 +404,12 @@ def bench_ssa(torch, np, arsel, workloads, lp=None, refresh: int = 1000, period:
         "acceptance_per_trial_at_refresh": {
             "uniform": round(float(np.mean(acc["uniform"])), 5),
             "learned": round(float(np.mean(acc["learned"])), 5)},
+        "law_chi2_p_first_steps": round(law_pvalue_rows(
+            np, np.concatenate(acc["law_a"]), np.arange(R * len(acc["law_a"])),
+            np.concatenate(acc["law_sel"])), 4),
+        "law_what": "the first step of each refresh segment (16384 realizations x "
+                    f"{steps // refresh} segments) against its state's alpha_j / alpha_0 "
+                    "(randomised PIT, 64 cells); the acceptance pass is a separate, untimed run",
         "mean_simulated_time": float(t.mean().item())}
     return out
 
@@ -460,6 +535,36 @@ def _scale_input(torch, M: int, K: int, seed: int):
     return a
 
 
+def bench_ceiling(torch, arsel, bufs, reps: int = 200):
+    """Achievable read bandwidth (arsel_probe_read) on the headline batch
+    shape and at 10^6 realizations: the same bytes read once with the
+    selection kernels' loads and nothing else, as graph replays over the same
+    rotating buffers (per-launch time includes the graph's launch gap)."""
+    nb, Mb, Rb = bufs.shape
+    out = {}
+    for tile in (0, 16):
+        sink = arsel.probe_read(bufs[0], Mb, Rb, Rb, tile)
+        sec = _timed(torch, lambda s: arsel.probe_read(bufs[s % nb], Mb, Rb, Rb, tile, sink=sink),
+                     reps)
+        nbytes = 4 * Mb * Rb
+        out["contiguous" if tile == 0 else f"soa_tile{tile}"] = {
+            "us_per_launch": round(sec * 1e6, 3), "GBs": round(nbytes / sec / 1e9, 1)}
+    big = _scale_input(torch, 1029, 1_000_000, 321)
+    for tile in (0, 16):
+        sink = arsel.probe_read(big, 1029, 1_000_000, 1_000_000, tile)
+        sec = _timed(torch, lambda s: arsel.probe_read(big, 1029, 1_000_000, 1_000_000, tile,
+                                                       sink=sink), 10)
+        out[("contiguous" if tile == 0 else f"soa_tile{tile}") + "_1e6x1029"] = {
+            "us_per_launch": round(sec * 1e6, 1), "GBs": round(4 * 1029e6 / sec / 1e9, 1)}
+    del big
+    # an empty launch: the probe on zero rows (one graph node, no work)
+    sink = arsel.probe_read(bufs[0], 0, 16, 16, 0)
+    out["empty_launch_us"] = round(_timed(torch, lambda s: arsel.probe_read(
+        bufs[0], 1, 16, 16, 0, sink=sink), reps) * 1e6, 3)
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_scale(torch, K: int = 1_000_000, reps: int = 10):
     """The dense kernel at the paper's scale claims: K realizations x M = 1029
     (SoA, lognormal(0,2) with 30% zeros) in one launch -- 10^6 (4.1 GB), and
@@ -567,6 +672,12 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
 
+    print("[bench] read-bandwidth ceiling", file=sys.stderr, flush=True)
+    ceiling = bench_ceiling(torch, arsel, bufs)
+    best = max(ceiling["contiguous"]["GBs"], ceiling["soa_tile16"]["GBs"])
+    roofline["probe_GBs"] = best
+    roofline["frac_of_probe"] = round(achieved / best, 4)
+
     cpu = None
     parity = "not checked (--no-cpu)"
     if not args.no_cpu:
@@ -607,6 +718,7 @@ def main() -> int:
                                "selection per realization per step, HIP graph of all steps",
                    "R": R, "M": M, "layout": "SoA", "buffers": NBUF, "seed": SEED},
         "roofline": roofline,
+        "read_ceiling": ceiling,
         "cpu_baseline": cpu,
         "acceptance": acceptance,
         "parity_last_step": parity,

@@ -137,11 +137,11 @@ int arsel_set_trial_lanes(arsel_ctx *ctx, int32_t lanes);
  * schedule split equal the previous host-sized call's reuses the lists already
  * on the device and launches one kernel; otherwise the lists are rebuilt and
  * copied through pinned memory.
- * Graph capture: a call with host_sizes NULL may be captured (the lists are
- * built on the device at replay); a call with host_sizes may be captured only
- * when it reuses the lists (make one eager call with the same sizes and
- * schedule first; the replay then reads the lists the context holds), and
- * returns ARSEL_ERR_ARG when it would rebuild them while the stream captures.
+ * Graph capture: while `stream` captures, host_sizes is ignored and the lists
+ * are built on the device inside the graph, so a replay reads no list that a
+ * later call leaves in the context.  Buffers the context outgrows are kept
+ * until arsel_destroy, so a graph stays valid while its context lives; the
+ * schedule is fixed into the graph when it is captured.
  */
 int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offsets,
                         int32_t K, const int64_t *host_sizes, uint64_t seed, uint64_t step,
@@ -326,6 +326,15 @@ typedef struct {
 int arsel_mlp_forward(arsel_ctx *ctx, const arsel_mlp *net, const int32_t *X, int32_t R,
                       const float *alpha, float *q_out, uint32_t *Q_out, void *stream);
 
+/* Inference forward path: on != 0 (the default) runs arsel_mlp_forward as one
+ * fused kernel per block of 32 states (features, the three layers, softmax
+ * and quantisation; activations in LDS and registers, no workspace) when
+ * H == 256, Kp % 32 == 0, Kp <= 1024, Mp % 16 == 0, Mp <= 1280 and W1, W2,
+ * W3 are 16-byte aligned; on == 0 forces the layer-by-layer kernels.  Both
+ * compute the same products and exponentials; q differs only by the order
+ * of the softmax row sums (a few ulp). */
+int arsel_set_mlp_fused(arsel_ctx *ctx, int32_t on);
+
 /* Training state: the network (its W1, W2, W3 are the BF16 copies refreshed by
  * each step) plus FP32 masters, gradients and Adam moments for the six
  * parameters in the order W1, b1, W2, b2, W3, b3 (shapes as in arsel_mlp).
@@ -358,6 +367,28 @@ int arsel_mlp_sync_bf16(arsel_ctx *ctx, const arsel_mlp_train *tr, void *stream)
 int arsel_gemm_bf16(arsel_ctx *ctx, const void *A, int64_t lda, int32_t a_kcontig, const void *B,
                     int64_t ldb, int32_t b_kcontig, int32_t M, int32_t N, int32_t K,
                     const float *bias, int32_t relu, float *C, int64_t ldc, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Measurement utility (not part of the method).
+ *
+ * Read bandwidth the device reaches on a rows x cols float matrix (DEVICE,
+ * row stride ld floats, 16-byte aligned, ld % 4 == 0) read once with the
+ * selection kernels' own 16-byte non-temporal loads, all of a workgroup's
+ * loads issued before any is consumed; timing it gives the achievable ceiling
+ * beside the data-sheet peak.
+ *   tile == 0: the matrix as one contiguous span (cols == ld), 4096 float4
+ *              per workgroup of 1024 threads;
+ *   tile in {4, 8, 16, 32, 64}, cols % tile == 0: the dense SoA pattern of
+ *              arsel_select: workgroup b reads `tile` consecutive columns of
+ *              every row (the XCD-aware tile order of the dense kernel).
+ * *grid_out receives the number of workgroups; sink (DEVICE, sink_len >= that
+ * number of uint32) receives each workgroup's maximum of the bits it read, so
+ * that no load can be dropped.  sink_len too small or more than 2^31 - 1
+ * workgroups: ARSEL_ERR_SIZE (nothing launched); a bad tile: ARSEL_ERR_ARG.
+ */
+int arsel_probe_read(arsel_ctx *ctx, const float *p, int32_t rows, int32_t cols, int64_t ld,
+                     int32_t tile, uint32_t *sink, int64_t sink_len, int64_t *grid_out,
+                     void *stream);
 
 #ifdef __cplusplus
 }

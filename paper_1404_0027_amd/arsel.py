@@ -98,6 +98,9 @@ _EXTRA_SIGNATURES = {
                         ctypes.c_int64, _P],
     "arsel_select_ragged": [_P, _P, _P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64,
                             ctypes.c_uint32, _P, _P, _P, _P],
+    "arsel_probe_read": [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                         _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P],
+    "arsel_set_mlp_fused": [_P, ctypes.c_int32],
     "arsel_get_schedule": [_P, ctypes.POINTER(Schedule)],
     "arsel_set_schedule": [_P, ctypes.POINTER(Schedule)],
     "arsel_set_dense_config": [_P, ctypes.c_int32, ctypes.c_int32],
@@ -220,6 +223,11 @@ def get_schedule(device=None) -> Schedule:
     s = Schedule()
     _check(lib().arsel_get_schedule(context(device), ctypes.byref(s)), "arsel_get_schedule")
     return s
+
+
+def set_mlp_fused(on: bool, device=None) -> None:
+    """Inference forward by the fused kernel (default) or layer by layer."""
+    _check(lib().arsel_set_mlp_fused(context(device), 1 if on else 0), "arsel_set_mlp_fused")
 
 
 def set_schedule(s: Schedule, device=None) -> None:
@@ -372,3 +380,23 @@ def gemm_bf16(A: torch.Tensor, lda: int, a_kcontig: bool, B: torch.Tensor, ldb: 
                                _stream(dev))
     _check(rc, "arsel_gemm_bf16")
     return C
+
+
+def probe_read(a: torch.Tensor, rows: int, cols: int, ld: int, tile: int = 0,
+               sink: torch.Tensor | None = None) -> torch.Tensor:
+    """Read-bandwidth probe (arsel_probe_read): reads the rows x cols float32
+    matrix `a` (row stride ld) once; returns the per-workgroup sink.  Pass the
+    sink of an earlier call to launch without allocating (graph capture)."""
+    dev = a.device
+    _need(a, torch.float32, rows * ld, "a", None)
+    grid = ctypes.c_int64(0)
+    rc = lib().arsel_probe_read(context(dev), None, rows, cols, ld, tile, None, 0,
+                                ctypes.byref(grid), _stream(dev))
+    if rc not in (0, -1, -2):
+        _check(rc, "arsel_probe_read")
+    if sink is None:
+        sink = torch.empty(max(grid.value, 1), dtype=torch.int32, device=dev)
+    rc = lib().arsel_probe_read(context(dev), _ptr(a), rows, cols, ld, tile, _ptr(sink),
+                                sink.numel(), ctypes.byref(grid), _stream(dev))
+    _check(rc, "arsel_probe_read")
+    return sink

@@ -36,9 +36,12 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     c->queue = nullptr;
     c->order = nullptr;
     c->order_bytes = 0;
+    c->order_dev = nullptr;
+    c->order_dev_bytes = 0;
     c->staging = nullptr;
     c->staging_bytes = 0;
     c->staging_event = nullptr;
+    c->mlp_fused = 1;
     c->ws = nullptr;
     c->ws_bytes = 0;
     c->ssa_tab = nullptr;
@@ -74,6 +77,8 @@ extern "C" int arsel_destroy(arsel_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->queue) (void)hipFree(ctx->queue);
     if (ctx->order) (void)hipFree(ctx->order);
+    if (ctx->order_dev) (void)hipFree(ctx->order_dev);
+    for (void *p : ctx->retired) (void)hipFree(p);
     if (ctx->staging_event) {
         (void)hipEventSynchronize(ctx->staging_event);
         (void)hipEventDestroy(ctx->staging_event);

@@ -21,6 +21,18 @@ __device__ __forceinline__ f32x4 load_stream4(const float *p)
     return __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
 }
 
+constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dealt round-robin
+
+// Workgroups are dealt to the XCDs round-robin, so consecutive block ids land
+// on different L2s.  Remap so that each XCD owns a contiguous range of tiles:
+// the two halves of a 128-byte line of an SoA row then meet in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int full = nb - nb % kXcds;
+    if (b >= full) return b;
+    return (b % kXcds) * (full / kXcds) + b / kXcds;
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10: 10 rounds of two 32x32->64 multiplies; the key is bumped by
 // the Weyl constants between rounds.

@@ -20,14 +20,19 @@ struct arsel_ctx {
     arsel_schedule sched;     // ragged schedule
     uint32_t *queue;          // device counters of the persistent ragged kernel, zero
                               // between calls (the kernel's last workgroup clears them)
-    int32_t *order;           // device work lists of the ragged kernel, grown on demand
-    size_t order_bytes;
+    int32_t *order;           // host-built work lists of the ragged kernel (reused while the
+    size_t order_bytes;       // sizes repeat), grown on demand
+    int32_t *order_dev;       // device-built work lists (rebuilt by every call that uses
+    size_t order_dev_bytes;   // them, graph replays included), grown on demand
+    std::vector<void *> retired;   // buffers replaced by larger ones: kept until
+                                   // arsel_destroy, so graphs captured earlier stay valid
     std::vector<int64_t> order_sizes;   // host sizes the work lists were built from,
     int32_t order_split;                // for this wave_max_m (-1: lists not reusable)
     uint32_t order_blocks, order_waves; // their lengths
     int32_t *staging;         // pinned host staging of the work lists
     size_t staging_bytes;
     hipEvent_t staging_event; // completion of the last staging copy
+    int mlp_fused;            // inference forward by the fused kernel when the shape allows
     void *ws;                 // MLP workspace (activations, gradients), grown on demand
     size_t ws_bytes;
     void *ssa_tab;            // packed dependency rows of the SSA run, grown on demand
@@ -54,6 +59,32 @@ inline size_t packed_lds_bytes(int32_t M, bool proposal)
     size_t t = 1;
     while (t < (size_t)M) t <<= 1;
     return ((size_t)M * 3 + t) * sizeof(uint32_t);
+}
+
+// Grow a context-owned device buffer to at least `need` bytes (contents not
+// kept).  The old buffer is retired, not freed: a graph captured earlier may
+// still hold its address, so it is released only by arsel_destroy.  Growth is
+// geometric, which bounds the retired memory by the final size.
+inline int ctx_grow(arsel_ctx *ctx, void **p, size_t *cap, size_t need)
+{
+    if (*cap >= need) return ARSEL_OK;
+    const size_t want = std::max(need, 2 * *cap);
+    void *q = nullptr;
+    if (hipMalloc(&q, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return ARSEL_ERR_ALLOC;
+    }
+    if (*p) {
+        try {
+            ctx->retired.push_back(*p);
+        } catch (...) {
+            (void)hipFree(q);
+            return ARSEL_ERR_ALLOC;
+        }
+    }
+    *p = q;
+    *cap = want;
+    return ARSEL_OK;
 }
 
 inline int ctx_activate(arsel_ctx *ctx)

@@ -491,13 +491,7 @@ struct Carver {
 
 static int ensure_ws(arsel_ctx *ctx, size_t bytes)
 {
-    if (ctx->ws_bytes >= bytes) return ARSEL_OK;
-    if (ctx->ws && hipFree(ctx->ws) != hipSuccess) return ARSEL_ERR_HIP;
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
-    if (hipMalloc(&ctx->ws, bytes) != hipSuccess) return ARSEL_ERR_ALLOC;
-    ctx->ws_bytes = bytes;
-    return ARSEL_OK;
+    return ctx_grow(ctx, &ctx->ws, &ctx->ws_bytes, bytes);
 }
 
 static int check_mlp(const arsel_mlp *n)
@@ -550,6 +544,281 @@ static int forward(arsel_ctx *ctx, const arsel_mlp *n, const int32_t *X, int32_t
     return gemm(g, true, true, s);
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference forward: one workgroup of kFW wavefronts per block of kFB
+// states runs the features, the three layers, the masked softmax and the
+// quantisation; f, h1 and h2 stay in LDS, z stays in the MFMA accumulators,
+// and the weights stream from L2 straight into MFMA operand registers.  The
+// k order of every product is the layer-by-layer kernels' (32-wide chunks in
+// increasing k) and the epilogues are theirs, so f, h1, h2, z and the
+// exponentials are bit-identical to the unfused path; only the softmax row
+// sums are added in another order.  Shapes: H = 256, Kp % 32 == 0 and
+// Kp <= kFMaxKp, Mp % 16 == 0 and Mp <= 16 * kFW * kFT3; others take the
+// unfused path.
+// ---------------------------------------------------------------------------
+constexpr int kFB = 32;            // states per workgroup (two 16-row MFMA tiles)
+constexpr int kFW = 8;             // wavefronts per workgroup
+constexpr int kFH = 256;           // hidden width
+constexpr int kFT3 = 10;           // layer-3 column tiles per wavefront (Mp <= 1280)
+constexpr int kFMaxKp = 1024;
+constexpr int kFPad = 8;           // LDS row padding (bf16)
+
+struct FusedFwd {
+    const int32_t *X;
+    const float *alpha;
+    const __bf16 *W1, *W2, *W3;
+    const float *b1, *b2, *b3;
+    float *q_out;
+    uint32_t *Q_out;
+    int32_t R, N, M, Kp, Mp, L;
+};
+
+__device__ __forceinline__ bf16x8 ld_frag(const __bf16 *p)
+{
+    return *reinterpret_cast<const bf16x8 *>(p);
+}
+
+// Max over the 16 lanes of each DPP row (rotations: every lane gets it).
+__device__ __forceinline__ float row16_max(float x)
+{
+    x = fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121, 0xF, 0xF, false)));
+    x = fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x122, 0xF, 0xF, false)));
+    x = fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xF, 0xF, false)));
+    x = fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false)));
+    return x;
+}
+
+// Inclusive sum over the 16 lanes of each DPP row; lane 15 of a row holds
+// the row's total (lanes without a source add 0).
+__device__ __forceinline__ float row16_sum_to_last(float x)
+{
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x112, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xF, 0xF, false));
+    return x;
+}
+
+// One hidden layer of the fused forward: dst[m][n] = bf16(relu(sum_k
+// src[m][k] W[n][k] + b[n])) for the block's 32 rows and 256 outputs; wave w
+// owns columns 32 w .. 32 w + 31.
+__device__ __forceinline__ void fused_hidden(const __bf16 *src, int lds_src, const __bf16 *W,
+                                             int K, const float *bias, __bf16 *dst, int lds_dst)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rl = lane & 15, kq = (lane >> 4) * 8;
+    f32x4m acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[i][c] = (f32x4m){0.f, 0.f, 0.f, 0.f};
+    const __bf16 *wrow[2] = {W + (int64_t)(32 * wave + rl) * K + kq,
+                             W + (int64_t)(32 * wave + 16 + rl) * K + kq};
+    bf16x8 b[2], bn[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) b[c] = ld_frag(wrow[c]);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        if (k0 + 32 < K) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) bn[c] = ld_frag(wrow[c] + k0 + 32);
+        }
+        bf16x8 a[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = ld_frag(src + (16 * i + rl) * lds_src + k0 + kq);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[c], acc[i][c], 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) b[c] = bn[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int n = 32 * wave + 16 * c + rl;
+        const float bb = bias[n];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[i][c][r] + bb;
+                v = v > 0.f ? v : 0.f;
+                dst[(16 * i + 4 * (lane >> 4) + r) * lds_dst + n] = (__bf16)v;
+            }
+    }
+}
+
+__global__ __launch_bounds__(kFW * 64) void k_mlp_forward_fused(FusedFwd f)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char fsm[];
+    const int ldf = f.Kp + kFPad, ldh = kFH + kFPad;
+    __bf16 *sF = reinterpret_cast<__bf16 *>(fsm);                    // [32][Kp + 8], later h2
+    __bf16 *sH1 = sF + kFB * ldf;                                     // [32][264]
+    float *sRed = reinterpret_cast<float *>(sH1 + kFB * ldh);         // [kFW][32]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rl = lane & 15, kq = (lane >> 4) * 8;
+    const int64_t r0 = (int64_t)blockIdx.x * kFB;
+
+    // features: bf16(log1p(x)) as the unfused feature kernel computes them
+    for (int e = tid; e < kFB * f.Kp; e += kFW * 64) {
+        const int m = e / f.Kp, i = e - m * f.Kp;
+        const int64_t r = r0 + m;
+        float v = 0.0f;
+        if (i < f.N && r < f.R) {
+            const int32_t x = f.X[r * f.N + i];
+            v = x > 0 ? __logf(1.0f + (float)x) : 0.0f;
+        }
+        sF[m * ldf + i] = (__bf16)v;
+    }
+    __syncthreads();
+    fused_hidden(sF, ldf, f.W1, f.Kp, f.b1, sH1, ldh);
+    __syncthreads();
+    __bf16 *sH2 = sF;
+    fused_hidden(sH1, ldh, f.W2, kFH, f.b2, sH2, ldh);
+    __syncthreads();
+
+    // layer 3: wave w owns column tiles w, w + kFW, ... (z in registers)
+    const int ntiles = f.Mp >> 4;
+    f32x4m acc[2][kFT3];
+#pragma unroll
+    for (int t = 0; t < kFT3; ++t)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) acc[i][t] = (f32x4m){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < kFH; k0 += 32) {
+        bf16x8 a[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = ld_frag(sH2 + (16 * i + rl) * ldh + k0 + kq);
+#pragma unroll
+        for (int t = 0; t < kFT3; ++t) {
+            const int tile = wave + kFW * t;
+            if (tile < ntiles) {
+                const bf16x8 b = ld_frag(f.W3 + (int64_t)(16 * tile + rl) * kFH + k0 + kq);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][t], 0, 0, 0);
+            }
+        }
+    }
+
+    // masked softmax over alpha_j > 0 and quantisation.  Lane (i, r) rows:
+    // m = 16 i + 4 (lane / 16) + r; column of tile t: n = 16 tile + lane % 16.
+    uint32_t sup[kFT3];
+    float rmax[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rmax[i][r] = -INFINITY;
+#pragma unroll
+    for (int t = 0; t < kFT3; ++t) {
+        sup[t] = 0;
+        const int tile = wave + kFW * t;
+        const int n = 16 * tile + rl;
+        const float bb = (tile < ntiles) ? f.b3[n] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + 16 * i + 4 * (lane >> 4) + r;
+                const float z = acc[i][t][r] + bb;
+                acc[i][t][r] = z;
+                if (tile < ntiles && n < f.M && row < f.R && f.alpha[row * f.M + n] > 0.0f) {
+                    sup[t] |= 1u << (4 * i + r);
+                    rmax[i][r] = fmaxf(rmax[i][r], z);
+                }
+            }
+    }
+    // row maxima: the 16 lanes of a DPP row, then the waves through LDS
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float x = row16_max(rmax[i][r]);
+            if (rl == 15) sRed[wave * kFB + 16 * i + 4 * (lane >> 4) + r] = x;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * i + 4 * (lane >> 4) + r;
+            float x = -INFINITY;
+            for (int w = 0; w < kFW; ++w) x = fmaxf(x, sRed[w * kFB + m]);
+            rmax[i][r] = x;
+        }
+    __syncthreads();
+    // exponentials (replacing z) and their row sums
+    float rsum[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rsum[i][r] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < kFT3; ++t)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float e = (sup[t] >> (4 * i + r)) & 1u ? expf(acc[i][t][r] - rmax[i][r]) : 0.0f;
+                acc[i][t][r] = e;
+                rsum[i][r] += e;
+            }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float x = row16_sum_to_last(rsum[i][r]);
+            if (rl == 15) sRed[wave * kFB + 16 * i + 4 * (lane >> 4) + r] = x;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * i + 4 * (lane >> 4) + r;
+            float x = 0.0f;
+            for (int w = 0; w < kFW; ++w) x += sRed[w * kFB + m];
+            rsum[i][r] = x;
+        }
+    const float qscale = ldexpf(1.0f, 31 - f.L);
+#pragma unroll
+    for (int t = 0; t < kFT3; ++t) {
+        const int tile = wave + kFW * t;
+        const int n = 16 * tile + rl;
+        if (tile >= ntiles || n >= f.M) continue;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + 16 * i + 4 * (lane >> 4) + r;
+                if (row >= f.R) continue;
+                const bool s = (sup[t] >> (4 * i + r)) & 1u;
+                const float q = s ? acc[i][t][r] / rsum[i][r] : 0.0f;
+                if (f.q_out) f.q_out[row * f.M + n] = q;
+                if (f.Q_out) {
+                    uint32_t Q = 0;
+                    if (s) {
+                        const float fl = floorf(q * qscale);
+                        Q = fl < 1.0f ? 1u : (uint32_t)fl;
+                    }
+                    f.Q_out[row * f.M + n] = Q;
+                }
+            }
+    }
+}
+
+static size_t fused_lds_bytes(int32_t Kp)
+{
+    return (size_t)kFB * (Kp + kFPad) * 2 + (size_t)kFB * (kFH + kFPad) * 2 + (size_t)kFW * kFB * 4;
+}
+
+static bool fused_ok(arsel_ctx *ctx, const arsel_mlp *n)
+{
+    const auto al = [](const void *p) { return ((uintptr_t)p % 16) == 0; };
+    return ctx->mlp_fused && n->H == kFH && n->Kp % 32 == 0 && n->Kp <= kFMaxKp &&
+           n->Mp % 16 == 0 && n->Mp <= 16 * kFW * kFT3 && al(n->W1) && al(n->W2) && al(n->W3) &&
+           fused_lds_bytes(n->Kp) <= ctx->lds_per_block;
+}
+
 static size_t fwd_bytes(const arsel_mlp *n, int32_t R)
 {
     return (size_t)R * (n->Kp * 2 + n->H * 4 + n->Mp * 4) + 8 * 256;
@@ -569,8 +838,30 @@ extern "C" int arsel_mlp_forward(arsel_ctx *ctx, const arsel_mlp *net, const int
     if (R == 0) return ARSEL_OK;
     if (!X || !alpha || (!q_out && !Q_out)) return ARSEL_ERR_NULL;
     if ((rc = ctx_activate(ctx))) return rc;
-    if ((rc = ensure_ws(ctx, fwd_bytes(net, R)))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if (fused_ok(ctx, net)) {
+        FusedFwd f;
+        f.X = X;
+        f.alpha = alpha;
+        f.W1 = (const __bf16 *)net->W1;
+        f.W2 = (const __bf16 *)net->W2;
+        f.W3 = (const __bf16 *)net->W3;
+        f.b1 = net->b1;
+        f.b2 = net->b2;
+        f.b3 = net->b3;
+        f.q_out = q_out;
+        f.Q_out = Q_out;
+        f.R = R;
+        f.N = net->N;
+        f.M = net->M;
+        f.Kp = net->Kp;
+        f.Mp = net->Mp;
+        f.L = ceil_log2_host(net->M);
+        hipLaunchKernelGGL(k_mlp_forward_fused, dim3((R + kFB - 1) / kFB), dim3(kFW * 64),
+                           fused_lds_bytes(net->Kp), s, f);
+        return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+    }
+    if ((rc = ensure_ws(ctx, fwd_bytes(net, R)))) return rc;
     Carver cv{(char *)ctx->ws, 0};
     Fwd f;
     if ((rc = forward(ctx, net, X, R, cv, f, s))) return rc;
@@ -703,4 +994,12 @@ extern "C" int arsel_mlp_sync_bf16(arsel_ctx *ctx, const arsel_mlp_train *tr, vo
     hipLaunchKernelGGL(k_cast_bf16, grid1(n2), dim3(256), 0, s, tr->master[2], (__bf16 *)n->W2, n2);
     hipLaunchKernelGGL(k_cast_bf16, grid1(n3), dim3(256), 0, s, tr->master[4], (__bf16 *)n->W3, n3);
     return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
+}
+
+// Forward path switch (tests compare the two; results are identical).
+extern "C" int arsel_set_mlp_fused(arsel_ctx *ctx, int32_t on)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    ctx->mlp_fused = on != 0;
+    return ARSEL_OK;
 }

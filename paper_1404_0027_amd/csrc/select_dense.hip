@@ -41,17 +41,6 @@ __device__ __forceinline__ void write_outcome(const DenseArgs &a, int k, const O
 
 constexpr int kMaxTile = 64;     // instances per tile (upper bound)
 constexpr int kBatch = 6;        // loads issued per thread before their LDS stores
-constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dealt round-robin
-
-// Workgroups are dealt to the XCDs round-robin, so consecutive block ids land
-// on different L2s.  Remap so that each XCD owns a contiguous range of tiles:
-// the two halves of a 128-byte line of an SoA row then meet in one L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb)
-{
-    const int full = nb - nb % kXcds;
-    if (b >= full) return b;
-    return (b % kXcds) * (full / kXcds) + b / kXcds;
-}
 
 // Running maximum of the raw bits of non-negative floats: for finite x >= 0
 // the float order is the unsigned order of the bits, and every negative,
@@ -202,13 +191,27 @@ __device__ __forceinline__ LaneDraw lane_draw(const Stream &st, uint32_t r, uint
     return d;
 }
 
-// Resolve one round from its draws: least accepted (trial << 32 | j) or kNoAccept.
+// The candidates' propensities of one round (both gathers issued together;
+// a rejected draw reads entry 0, whose value is then ignored).
+struct RoundVals {
+    float a, b;
+};
+
 template <class Acc>
-__device__ __forceinline__ uint64_t resolve_round(const Acc &A, const LaneDraw &d, double envd,
-                                                  uint32_t r)
+__device__ __forceinline__ RoundVals gather_round(const Acc &A, const LaneDraw &d)
 {
-    const bool acca = d.ja != kNoCand && grid_u(d.ua) * envd < (double)A(d.ja);
-    const bool accb = d.jb != kNoCand && grid_u(d.ub) * envd < (double)A(d.jb);
+    return {A(d.ja != kNoCand ? d.ja : 0u), A(d.jb != kNoCand ? d.jb : 0u)};
+}
+
+// Decide one round from its draws and gathered values: least accepted
+// (trial << 32 | j) or kNoAccept.  envs is the envelope times 2^-32 (exact),
+// so w * envs is the real number u * env rounded once, as fl64(u * env) with
+// u = w 2^-32.
+__device__ __forceinline__ uint64_t decide_round(const LaneDraw &d, RoundVals x, double envs,
+                                                 uint32_t r)
+{
+    const bool acca = (d.ja != kNoCand) & ((double)d.ua * envs < (double)x.a);
+    const bool accb = (d.jb != kNoCand) & ((double)d.ub * envs < (double)x.b);
     const uint64_t ma = __ballot(acca), mb = __ballot(accb);
     if ((ma | mb) == 0) return kNoAccept;
     const uint64_t t0 = (uint64_t)r * kRoundTrials;
@@ -217,12 +220,29 @@ __device__ __forceinline__ uint64_t resolve_round(const Acc &A, const LaneDraw &
     return ((t0 + 2 * (uint64_t)lb + 1) << 32) | readlane_u32(d.jb, lb);
 }
 
+template <class Acc>
+__device__ __forceinline__ uint64_t resolve_round(const Acc &A, const LaneDraw &d, double envs,
+                                                  uint32_t r)
+{
+    return decide_round(d, gather_round(A, d), envs, r);
+}
+
+// Envelope scaled by 2^-32 for decide_round (exact in binary64).
+__device__ __forceinline__ double scaled_env(float env)
+{
+    return (double)env * 0x1p-32;
+}
+
+// Row stride of the partial maxima (one word more than the 64 slots, so that
+// a wavefront reading one instance's slots touches 64 different banks).
+constexpr int kPartStride = 65;
+
 // Per-instance state of a tile.
 struct TileState {
     uint64_t best[kMaxTile];      // least accepted (trial << 32 | j) so far
     uint64_t open;                // instances whose rounds are still handed out
     uint32_t next[kMaxTile];      // next round to hand out
-    double env[kMaxTile];
+    double env[kMaxTile];         // envelope times 2^-32 (scaled_env)
     float amax[kMaxTile];
     float alpha0[kMaxTile];
     int32_t index[kMaxTile];      // 0 in the trial phase, < 0 decided status
@@ -256,7 +276,8 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
         thresh = lemire_threshold(M);
 #pragma unroll
         for (int r = 0; r < kPreRounds; ++r)
-            if (own && (uint32_t)r < rounds) pre[r] = lane_draw(st_own, r, M, thresh, a.t_max);
+            pre[r] = (own && (uint32_t)r < rounds) ? lane_draw(st_own, r, M, thresh, a.t_max)
+                                                   : LaneDraw{kNoCand, 0u, kNoCand, 0u};
     };
     const bool fused = stage_tile<NW>(a, lds, k0, nk, bcast, mx, mid);
     if (fused) {
@@ -275,7 +296,7 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
         if (rl < qpr) {
             const int slot = wave * 4 + (lane >> 4);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) part[slot * a.tk + 4 * rl + c] = mx[c];
+            for (int c = 0; c < 4; ++c) part[(4 * rl + c) * kPartStride + slot] = mx[c];
         }
     }
     if (tid == 0) ts.open = 0;
@@ -286,9 +307,16 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
         const int k = k0 + t;
         const ContigAcc acc{lds + (bcast ? 0 : t * a.mp)};
         const float *bk = a.bound ? a.bound + k : nullptr;
+        // the candidates of the pre-drawn rounds do not depend on the
+        // envelope: gather them all before the maximum is reduced
+        RoundVals pv[kPreRounds];
+        if (t == wave) {
+#pragma unroll
+            for (int rr = 0; rr < kPreRounds; ++rr) pv[rr] = gather_round(acc, pre[rr]);
+        }
         ScanState sc;
         uint32_t mb = 0;
-        if (fused) mb = wave_max_u32(lane < NW * 4 ? part[lane * a.tk + t] : 0u);
+        if (fused) mb = wave_max_u32(lane < NW * 4 ? part[t * kPartStride + lane] : 0u);
         if (fused && mb < kInvalidBits && !bk) {
             // certified valid: alpha_max from the fused maximum
             sc.scanned = true;
@@ -304,14 +332,14 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
         uint64_t key = kNoAccept;
         uint32_t r = 0;
         if (!sc.decided) {
-            const double envd = (double)sc.env;
+            const double envs = scaled_env(sc.env);
             // instances beyond the first NW of a tile start at round 0 in the
             // batches below
             if (t == wave) {
 #pragma unroll
                 for (int rr = 0; rr < kPreRounds; ++rr) {
                     if ((uint32_t)rr < rounds && key == kNoAccept) {
-                        key = resolve_round(acc, pre[rr], envd, rr);
+                        key = decide_round(pre[rr], pv[rr], envs, rr);
                         r = rr + 1;
                     }
                 }
@@ -331,7 +359,7 @@ __global__ __launch_bounds__(NW * 64) void k_select_tile(DenseArgs a)
             ts.written[t] = (sc.decided || key != kNoAccept) ? 1 : 0;
             ts.alpha0[t] = sc.o.alpha0;
             ts.amax[t] = sc.amax;
-            ts.env[t] = (double)sc.env;
+            ts.env[t] = scaled_env(sc.env);
             ts.best[t] = key;
             ts.next[t] = r;
             if (!sc.decided && key == kNoAccept && r < rounds)
@@ -495,7 +523,7 @@ extern "C" int arsel_select(arsel_ctx *ctx, const float *alpha, int32_t M, int32
         }
         a.tk = tk;
         const size_t lds = (bcast ? 1 : (size_t)tk) * (size_t)a.mp * sizeof(float) +
-                           (size_t)tk * 16 * 4 * sizeof(uint32_t);   // partial maxima: 16 waves x 4 rows
+                           (size_t)tk * kPartStride * sizeof(uint32_t);   // partial maxima: up to 64 slots per instance
         const int grid = (K + tk - 1) / tk;
         rc = launch_tile(ctx, a, grid, lds, s);
     } else {

@@ -250,18 +250,6 @@ static int launch_ragged(arsel_ctx *ctx, const RaggedArgs &a, size_t lds, hipStr
     return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
 }
 
-// Grow a device buffer (contents not kept).
-static int grow(void **p, size_t *cap, size_t need)
-{
-    if (*cap >= need) return ARSEL_OK;
-    if (*p && hipFree(*p) != hipSuccess) return ARSEL_ERR_HIP;
-    *p = nullptr;
-    *cap = 0;
-    if (hipMalloc(p, need) != hipSuccess) return ARSEL_ERR_ALLOC;
-    *cap = need;
-    return ARSEL_OK;
-}
-
 }  // namespace arsel
 
 using namespace arsel;
@@ -283,17 +271,31 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
     const size_t lds = std::max<size_t>((size_t)sc.lds_max_m, (size_t)nw * sc.wave_max_m) * sizeof(float);
     if (lds > ctx->lds_per_block - 2048) return ARSEL_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
-
-    const int32_t *held = ctx->order;
-    rc = grow((void **)&ctx->order, &ctx->order_bytes, 2 * (size_t)K * sizeof(int32_t));
-    if (rc || ctx->order != held) ctx->order_split = -1;
-    if (rc) return rc;
+    // Under graph capture the lists are built on the device, inside the graph,
+    // in their own buffer: a replay then depends on no list a later call
+    // leaves in the context.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return ARSEL_ERR_HIP;
+    if (cap != hipStreamCaptureStatusNone) host_sizes = nullptr;
+    const size_t list_bytes = 2 * (size_t)K * sizeof(int32_t);
+    int32_t *lists;
+    if (host_sizes) {
+        const int32_t *held = ctx->order;
+        rc = ctx_grow(ctx, (void **)&ctx->order, &ctx->order_bytes, list_bytes);
+        if (rc || ctx->order != held) ctx->order_split = -1;
+        if (rc) return rc;
+        lists = ctx->order;
+    } else {
+        if ((rc = ctx_grow(ctx, (void **)&ctx->order_dev, &ctx->order_dev_bytes, list_bytes)))
+            return rc;
+        lists = ctx->order_dev;
+    }
 
     RaggedArgs a;
     a.alpha = alpha;
     a.offsets = offsets;
-    a.list_block = ctx->order;
-    a.list_wave = ctx->order + K;
+    a.list_block = lists;
+    a.list_wave = lists + K;
     a.queue = ctx->queue;
     a.index = index;
     a.alpha0 = alpha0;
@@ -314,12 +316,6 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
         const bool same = ctx->order_split == sc.wave_max_m && ctx->order_sizes.size() == (size_t)K &&
                           std::equal(host_sizes, host_sizes + K, ctx->order_sizes.begin());
         if (!same) {
-            // Rebuilding copies the lists from host memory, which a captured
-            // graph would replay from a buffer later calls overwrite: under
-            // capture only calls that reuse the lists are accepted.
-            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-            if (hipStreamIsCapturing(s, &cap) != hipSuccess) return ARSEL_ERR_HIP;
-            if (cap != hipStreamCaptureStatusNone) return ARSEL_ERR_ARG;
             ctx->order_split = -1;
             // Longest first within each list; the lists go to the device through a
             // pinned staging buffer (reused once the previous copy has finished).
@@ -373,9 +369,7 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
         a.n_block = ctx->order_blocks;
         a.n_wave = ctx->order_waves;
     } else {
-        ctx->order_split = -1;
-        if ((rc = build_lists_on_device(offsets, K, sc.wave_max_m, ctx->order, ctx->order + K,
-                                        ctx->queue, s)))
+        if ((rc = build_lists_on_device(offsets, K, sc.wave_max_m, lists, lists + K, ctx->queue, s)))
             return rc;
         a.counts = ctx->queue + 2;
         a.n_block = a.n_wave = 0;
@@ -387,3 +381,4 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
     default: return ARSEL_ERR_ARG;
     }
 }
+

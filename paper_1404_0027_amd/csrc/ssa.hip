@@ -798,13 +798,7 @@ static int ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps
     const size_t per_wave = (size_t)(net->N + (prop ? 2 : 1) * (size_t)net->M) * 4;
     if (per_wave > ctx->lds_per_block) return ARSEL_ERR_SIZE;
     const size_t tab_bytes = (size_t)net->M * kDepMax * sizeof(int4);
-    if (ctx->ssa_tab_bytes < tab_bytes) {
-        if (ctx->ssa_tab && hipFree(ctx->ssa_tab) != hipSuccess) return ARSEL_ERR_HIP;
-        ctx->ssa_tab = nullptr;
-        ctx->ssa_tab_bytes = 0;
-        if (hipMalloc(&ctx->ssa_tab, tab_bytes) != hipSuccess) return ARSEL_ERR_ALLOC;
-        ctx->ssa_tab_bytes = tab_bytes;
-    }
+    if ((rc = ctx_grow(ctx, &ctx->ssa_tab, &ctx->ssa_tab_bytes, tab_bytes))) return rc;
     int4 *tab = (int4 *)ctx->ssa_tab;
     hipStream_t s = (hipStream_t)stream;
     const int64_t entries = (int64_t)net->M * kDepMax;

@@ -211,21 +211,28 @@ def test_ragged_counters_cleared_between_calls(gpu):
 
 
 def test_ragged_graph_capture_replays_match_eager(gpu):
-    """Captured calls (one reusing host-built lists, one with device-built
-    lists) replayed several times, with eager calls on other sizes between
-    the replays: every replay equals the eager result; a call that would
-    rebuild host lists during capture is refused."""
+    """Captured calls (host sizes whose lists were built eagerly, host sizes
+    never seen before, device-built lists) replayed several times with eager
+    calls between the replays that rebuild the host lists for other sizes and
+    outgrow the device list buffer: every replay equals the oracle (under
+    capture the lists are built inside the graph; outgrown buffers are kept
+    while the context lives)."""
     A, B = _sized_batch(11), _sized_batch(12)
+    C = _sized_batch(13, K=3000)
     a = torch.from_numpy(A[0]).cuda()
     off = torch.from_numpy(A[1]).cuda()
     b = torch.from_numpy(B[0]).cuda()
     offb = torch.from_numpy(B[1]).cuda()
-    K = A[1].shape[0] - 1
+    c = torch.from_numpy(C[0]).cuda()
+    offc = torch.from_numpy(C[1]).cuda()
+    K, KB = A[1].shape[0] - 1, B[1].shape[0] - 1
     ref, _, _ = oracle.select_ragged(A[0], A[1], seed=8, step=4, threads=8)
+    refb, _, _ = oracle.select_ragged(B[0], B[1], seed=6, step=2, threads=8)
     arsel.select_ragged(a, off, seed=8, step=4, host_offsets=A[1])       # eager: lists built
     torch.cuda.synchronize()
     out_h = torch.full((K,), -7, dtype=torch.int32, device="cuda")
     out_d = torch.full((K,), -7, dtype=torch.int32, device="cuda")
+    out_b = torch.full((KB,), -7, dtype=torch.int32, device="cuda")
     g = torch.cuda.CUDAGraph()
     cap = torch.cuda.Stream()
     cap.wait_stream(torch.cuda.current_stream())
@@ -233,33 +240,26 @@ def test_ragged_graph_capture_replays_match_eager(gpu):
         with torch.cuda.graph(g, stream=cap, capture_error_mode="relaxed"):
             arsel.select_ragged(a, off, seed=8, step=4, host_offsets=A[1], index=out_h)
             arsel.select_ragged(a, off, seed=8, step=4, index=out_d)
+            arsel.select_ragged(b, offb, seed=6, step=2, host_offsets=B[1], index=out_b)
     torch.cuda.synchronize()
     for rep in range(4):
-        out_h.fill_(-7)
-        out_d.fill_(-7)
+        for o in (out_h, out_d, out_b):
+            o.fill_(-7)
         g.replay()
         torch.cuda.synchronize()
-        assert np.array_equal(out_h.cpu().numpy(), ref), rep
-        assert np.array_equal(out_d.cpu().numpy(), ref), rep
-        # eager work between replays: another batch, device-built lists
-        ob, _, _ = arsel.select_ragged(b, offb, seed=1, step=rep)
+        assert np.array_equal(out_h.cpu().numpy(), ref), ("host sizes, built before", rep)
+        assert np.array_equal(out_d.cpu().numpy(), ref), ("device lists", rep)
+        assert np.array_equal(out_b.cpu().numpy(), refb), ("host sizes, not built before", rep)
+        # eager work between replays: host lists for other sizes, then a larger
+        # batch with device-built lists (the list buffers grow)
+        arsel.select_ragged(b, offb, seed=1, step=rep, host_offsets=B[1])
+        oc, _, _ = arsel.select_ragged(c, offc, seed=1, step=rep)
         torch.cuda.synchronize()
-    # the captured host-list call reads the context's lists: rebuild them for A
-    arsel.select_ragged(a, off, seed=8, step=4, host_offsets=A[1])
-    torch.cuda.synchronize()
-    g.replay()
-    torch.cuda.synchronize()
-    assert np.array_equal(out_h.cpu().numpy(), ref)
-    # rebuilding host lists under capture is refused
-    g2 = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(cap):
-        with pytest.raises(arsel.ArselError):
-            with torch.cuda.graph(g2, stream=cap, capture_error_mode="relaxed"):
-                arsel.select_ragged(b, offb, seed=1, step=0, host_offsets=B[1])
-    torch.cuda.synchronize()
-    # and the context still works afterwards
+    # the context still serves eager calls after the replays
     g_, o_ = _ragged_both(B[0], B[1], seed=2, step=3)
-    assert_same(g_, o_, "after a refused capture")
+    assert_same(g_, o_, "after the replays")
+    g_, o_ = _ragged_both(A[0], A[1], seed=2, step=5, host=False)
+    assert_same(g_, o_, "device lists after the replays")
 
 
 def test_ragged_device_lists_large_batch(gpu):
