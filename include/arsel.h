@@ -149,6 +149,27 @@ int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offse
                         void *stream);
 
 /*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): arsel_select_ragged with
+ * the work lists built on the device (as with host_sizes NULL), whose lists
+ * and counters live in a static device array of the library instead of the
+ * context.  The call makes no allocation of any kind (no hipMalloc, hipFree,
+ * pinned host memory or copies) and launches two kernels.  The array holds
+ * the counters and the lists of at most 65536 instances (about 512 KB); each
+ * GPU the library runs on holds its own copy until the process ends.
+ * K > 65536: ARSEL_ERR_SIZE; the array's address could not be found when the
+ * context was created: ARSEL_ERR_HIP.  Other arguments and results as
+ * arsel_select_ragged (bit-identical for any schedule).  Every call on one
+ * GPU, from any context, uses that GPU's one array: calls that overlap on a
+ * GPU race and must be serialised (one stream, or events between streams).
+ * Each call sets every counter it reads, so nothing an earlier call left in
+ * the array affects it.
+ */
+int arsel_select_ragged_noalloc(arsel_ctx *ctx, const float *alpha, const int64_t *offsets,
+                                int32_t K, uint64_t seed, uint64_t step, uint32_t t_max,
+                                int32_t *index, float *alpha0, uint32_t *trials, void *stream);
+
+/*
  * Schedule of arsel_select_ragged (chosen by the autotuner).
  *   wave_max_m:  instances with M <= wave_max_m are run by one wavefront each
  *                (staged in that wave's LDS slice); larger ones by a whole

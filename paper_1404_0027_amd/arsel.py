@@ -98,6 +98,8 @@ _EXTRA_SIGNATURES = {
                         ctypes.c_int64, _P],
     "arsel_select_ragged": [_P, _P, _P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64,
                             ctypes.c_uint32, _P, _P, _P, _P],
+    "arsel_select_ragged_noalloc": [_P, _P, _P, ctypes.c_int32, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_uint32, _P, _P, _P, _P],
     "arsel_probe_read": [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                          _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P],
     "arsel_set_mlp_fused": [_P, ctypes.c_int32],
@@ -284,6 +286,38 @@ def select_ragged(alpha: torch.Tensor, offsets: torch.Tensor, *, seed: int, step
                                    _ptr(alpha0), _ptr(trials), _stream(dev))
     _check(rc, "arsel_select_ragged")
     return index, alpha0, trials
+
+
+RAGGED_NOALLOC_MAX_K = 65536
+
+
+def select_ragged_noalloc(alpha: torch.Tensor, offsets: torch.Tensor, *, seed: int,
+                          step: int = 0, t_max: int = 4096, index: torch.Tensor,
+                          alpha0: torch.Tensor | None = None,
+                          trials: torch.Tensor | None = None) -> None:
+    """Uneven batch without any allocation (arsel_select_ragged_noalloc).
+
+    The caller passes every output tensor; the work lists and counters live in
+    the library's static per-GPU scratch array (K <= RAGGED_NOALLOC_MAX_K).
+    Calls on one GPU share that array: do not overlap them.
+    """
+    dev = alpha.device
+    if not isinstance(offsets, torch.Tensor) or offsets.dtype != torch.int64:
+        raise ArselError("offsets must be an int64 tensor")
+    K = offsets.numel() - 1
+    if K < 0:
+        raise ArselError("offsets needs K+1 entries")
+    _need(offsets, torch.int64, K + 1, "offsets", dev)
+    _need(alpha, torch.float32, 0, "alpha", None)
+    _need(index, torch.int32, K, "index", dev)
+    if alpha0 is not None:
+        _need(alpha0, torch.float32, K, "alpha0", dev)
+    if trials is not None:
+        _need(trials, torch.int32, K, "trials", dev)
+    rc = lib().arsel_select_ragged_noalloc(context(dev), _ptr(alpha), _ptr(offsets), K,
+                                           seed & (2**64 - 1), step & (2**64 - 1), t_max,
+                                           _ptr(index), _ptr(alpha0), _ptr(trials), _stream(dev))
+    _check(rc, "arsel_select_ragged_noalloc")
 
 
 def select_proposal(alpha: torch.Tensor, Q: torch.Tensor, *, seed: int, step: int = 0,

@@ -47,6 +47,7 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     c->ssa_tab = nullptr;
     c->ssa_tab_bytes = 0;
     c->ln_tab = nullptr;
+    c->scratch = nullptr;
     double tab[2 * (kLnTabHi - kLnTabLo + 1)];
     for (int i = kLnTabLo; i <= kLnTabHi; ++i) {
         tab[2 * (i - kLnTabLo)] = log((double)i / 128.0);
@@ -64,6 +65,9 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
         (void)hipSetDevice(prev);
         return ARSEL_ERR_ALLOC;
     }
+    // the no-allocation ragged call finds its scratch here, once per context,
+    // with the context's device current; a failure only disables that call
+    if (arsel::ragged_scratch_address(&c->scratch) != ARSEL_OK) c->scratch = nullptr;
     (void)hipSetDevice(prev);
     *out = c;
     return ARSEL_OK;

@@ -38,6 +38,8 @@ struct arsel_ctx {
     void *ssa_tab;            // packed dependency rows of the SSA run, grown on demand
     size_t ssa_tab_bytes;
     double *ln_tab;           // {ln(i/128), 128/i} for i = 96..192 (the run's logarithm)
+    void *scratch;            // this device's address of the static scratch array of
+                              // arsel_select_ragged_noalloc (null if it could not be found)
 };
 
 // Grid of the run's table-driven logarithm: c_i = i / 128, i in [96, 192].
@@ -60,6 +62,10 @@ inline size_t packed_lds_bytes(int32_t M, bool proposal)
     while (t < (size_t)M) t <<= 1;
     return ((size_t)M * 3 + t) * sizeof(uint32_t);
 }
+
+// Address of the static scratch array of arsel_select_ragged_noalloc on the
+// current device (select_ragged.hip).
+int ragged_scratch_address(void **out);
 
 // Grow a context-owned device buffer to at least `need` bytes (contents not
 // kept).  The old buffer is retired, not freed: a graph captured earlier may

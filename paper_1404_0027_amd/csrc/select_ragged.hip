@@ -250,6 +250,28 @@ static int launch_ragged(arsel_ctx *ctx, const RaggedArgs &a, size_t lds, hipStr
     return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
 }
 
+// Scratch of arsel_select_ragged_noalloc: the launch counters (padded to
+// 256 bytes) and the two work lists of at most kNoAllocMaxK instances, in a
+// file-scope device array.  Each GPU the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (ragged_scratch_address).
+constexpr int32_t kNoAllocMaxK = kOrderMaxK;
+constexpr size_t kScratchQueueWords = 64;
+static __device__ __align__(256) uint32_t scratch[kScratchQueueWords + 2 * (size_t)kNoAllocMaxK];
+
+int ragged_scratch_address(void **out)
+{
+    *out = nullptr;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+        (void)hipGetLastError();
+        return ARSEL_ERR_HIP;
+    }
+    *out = p;
+    return ARSEL_OK;
+}
+
+
 }  // namespace arsel
 
 using namespace arsel;
@@ -382,3 +404,54 @@ extern "C" int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int
     }
 }
 
+// The same selection with the work lists built on the device in the GPU's
+// static scratch array: no allocation of any kind.  k_ragged_order sets every
+// counter before the selection kernel reads it, so nothing left in the array
+// by an earlier call (or an interrupted one) is read.
+extern "C" int arsel_select_ragged_noalloc(arsel_ctx *ctx, const float *alpha,
+                                           const int64_t *offsets, int32_t K, uint64_t seed,
+                                           uint64_t step, uint32_t t_max, int32_t *index,
+                                           float *alpha0, uint32_t *trials, void *stream)
+{
+    if (!ctx) return ARSEL_ERR_NULL;
+    if (K < 0 || K > kNoAllocMaxK) return ARSEL_ERR_SIZE;
+    if (K == 0) return ARSEL_OK;
+    if (!alpha || !offsets || !index) return ARSEL_ERR_NULL;
+    if (!ctx->scratch) return ARSEL_ERR_HIP;
+    int rc = ctx_activate(ctx);
+    if (rc) return rc;
+    (void)hipGetLastError();   // a stale error of earlier work is not this call's
+    const arsel_schedule &sc = ctx->sched;
+    const int nw = sc.block_waves;
+    const size_t lds = std::max<size_t>((size_t)sc.lds_max_m, (size_t)nw * sc.wave_max_m) * sizeof(float);
+    if (lds > ctx->lds_per_block - 2048) return ARSEL_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+
+    uint32_t *queue = static_cast<uint32_t *>(ctx->scratch);
+    int32_t *lists = reinterpret_cast<int32_t *>(queue + kScratchQueueWords);
+    RaggedArgs a;
+    a.alpha = alpha;
+    a.offsets = offsets;
+    a.list_block = lists;
+    a.list_wave = lists + K;
+    a.counts = queue + 2;
+    a.n_block = a.n_wave = 0;
+    a.queue = queue;
+    a.index = index;
+    a.alpha0 = alpha0;
+    a.trials = trials;
+    a.seed = seed;
+    a.step = step;
+    a.t_max = t_max;
+    a.lds_max_m = sc.lds_max_m;
+    a.wave_max_m = sc.wave_max_m;
+    hipLaunchKernelGGL(k_ragged_order, dim3(1), dim3(kOrderThreads), 0, s, offsets, K,
+                       sc.wave_max_m, lists, lists + K, queue);
+    if (hipGetLastError() != hipSuccess) return ARSEL_ERR_HIP;
+    switch (nw) {
+    case 4: return launch_ragged<4>(ctx, a, lds, s);
+    case 8: return launch_ragged<8>(ctx, a, lds, s);
+    case 16: return launch_ragged<16>(ctx, a, lds, s);
+    default: return ARSEL_ERR_ARG;
+    }
+}
