@@ -122,16 +122,21 @@ int arsel_set_dense_config(arsel_ctx *ctx, int32_t tile, int32_t waves);
 int arsel_set_trial_lanes(arsel_ctx *ctx, int32_t lanes);
 
 /*
- * Uneven batch in one persistent launch: instance k has
- * M_k = offsets[k+1] - offsets[k] reactions at alpha[offsets[k] ..] (AoS).
- * offsets is a DEVICE array of K+1 int64; host_sizes is NULL or a HOST array
- * of the K sizes.  The instances are split into a workgroup list and a
- * wavefront list (M_k above or up to the schedule's wave_max_m) taken longest
- * first by power-of-two size class: with host_sizes the lists are built on the
- * host, otherwise on the device (one extra small kernel per call; for K above
+ * Uneven batch: instance k has M_k = offsets[k+1] - offsets[k] reactions at
+ * alpha[offsets[k] ..] (AoS).  offsets is a DEVICE array of K+1 int64;
+ * host_sizes is NULL or a HOST array of the K sizes.  Instances with M_k up
+ * to the schedule's wave_max_m are selected by one wavefront each, staged in
+ * LDS.  The larger ones are streamed once for alpha_max and an estimate of
+ * alpha_0; those expected to need more than 512 trials are cut into chunks
+ * spread over every workgroup, each chunk staged in LDS and tested against
+ * all of the instance's trials (so the row is read once more at streaming
+ * speed and no candidate costs a DRAM access of its own), and the others run
+ * their trials by one wavefront each.  Four launches per call: scan, split,
+ * chunks, pick.  With host_sizes the work lists are built on the host,
+ * otherwise on the device (one extra small kernel per call; for K above
  * 65536 the device lists are in arbitrary order).  M_k == 0 reports -1.
  * Results are bit-identical to arsel_select on each instance with instance
- * id k, whatever the schedule or order.
+ * id k, whatever the schedule, order or split.
  * The context holds this call's work lists and counters: calls on one context
  * must not overlap (issue them on one stream).  A call whose host_sizes and
  * schedule split equal the previous host-sized call's reuses the lists already
@@ -151,19 +156,22 @@ int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offse
 /*
  * For callers that cannot allocate memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): arsel_select_ragged with
- * the work lists built on the device (as with host_sizes NULL), whose lists
- * and counters live in a static device array of the library instead of the
- * context.  The call makes no allocation of any kind (no hipMalloc, hipFree,
- * pinned host memory or copies) and launches two kernels.  The array holds
- * the counters and the lists of at most 65536 instances (about 512 KB); each
- * GPU the library runs on holds its own copy until the process ends.
+ * the work lists built on the device (as with host_sizes NULL), whose lists,
+ * counters, keys and per-instance accumulators live in a static device array
+ * of the library instead of the context.  The call makes no allocation of
+ * any kind (no hipMalloc, hipFree, pinned host memory or copies) and launches
+ * five kernels.  The array holds the state of at most 65536 instances (about
+ * 9.2 MB); each GPU the library runs on holds its own copy until the process
+ * ends.  Each large instance is scanned in at most two items and a hard one
+ * is one chunk, so a hard row is tested by one workgroup piece by piece
+ * (slower than arsel_select_ragged for batches of few large rows).
  * K > 65536: ARSEL_ERR_SIZE; the array's address could not be found when the
  * context was created: ARSEL_ERR_HIP.  Other arguments and results as
  * arsel_select_ragged (bit-identical for any schedule).  Every call on one
  * GPU, from any context, uses that GPU's one array: calls that overlap on a
  * GPU race and must be serialised (one stream, or events between streams).
- * Each call sets every counter it reads, so nothing an earlier call left in
- * the array affects it.
+ * Each call sets every counter it reads and leaves the accumulators zero, so
+ * nothing an earlier call left in the array affects it.
  */
 int arsel_select_ragged_noalloc(arsel_ctx *ctx, const float *alpha, const int64_t *offsets,
                                 int32_t K, uint64_t seed, uint64_t step, uint32_t t_max,
@@ -171,15 +179,17 @@ int arsel_select_ragged_noalloc(arsel_ctx *ctx, const float *alpha, const int64_
 
 /*
  * Schedule of arsel_select_ragged (chosen by the autotuner).
- *   wave_max_m:  instances with M <= wave_max_m are run by one wavefront each
- *                (staged in that wave's LDS slice); larger ones by a whole
- *                workgroup.
- *   block_waves: wavefronts per workgroup (4, 8 or 16).
- *   lds_max_m:   workgroup instances with M <= lds_max_m are staged in LDS;
- *                larger ones are gathered from global memory.
- *   blocks_per_cu: persistent workgroups launched per compute unit (1..8).
- * max(lds_max_m, block_waves * wave_max_m) floats of LDS must fit in one
- * workgroup (ARSEL_ERR_ARG otherwise).  The schedule never changes results.
+ *   wave_max_m:  instances with M <= wave_max_m are run by one wavefront each,
+ *                staged in that wave's LDS slice; larger ones are scanned
+ *                first and split into easy and hard.
+ *   block_waves: wavefronts per workgroup of the pick launch (4, 8 or 16).
+ *   lds_max_m:   floats of a hard row staged in LDS at a time by the chunk
+ *                launch, also the chunk length (rounded down to a multiple of
+ *                4 and clamped to [2048, 16380]; 0 selects 16380).
+ *   blocks_per_cu: pick workgroups launched per compute unit (1..8).
+ * block_waves * wave_max_m floats (and the hard piece) must fit in one
+ * workgroup's LDS (ARSEL_ERR_ARG otherwise).  The schedule never changes
+ * results.
  */
 typedef struct {
     int32_t wave_max_m;
@@ -347,13 +357,13 @@ typedef struct {
 int arsel_mlp_forward(arsel_ctx *ctx, const arsel_mlp *net, const int32_t *X, int32_t R,
                       const float *alpha, float *q_out, uint32_t *Q_out, void *stream);
 
-/* Inference forward path: on != 0 (the default) runs arsel_mlp_forward as one
- * fused kernel per block of 32 states (features, the three layers, softmax
- * and quantisation; activations in LDS and registers, no workspace) when
+/* Inference forward path: on != 0 runs arsel_mlp_forward as one fused kernel
+ * per block of 32 states (features, the three layers, softmax and
+ * quantisation; activations in LDS and registers, no workspace) when
  * H == 256, Kp % 32 == 0, Kp <= 1024, Mp % 16 == 0, Mp <= 1280 and W1, W2,
- * W3 are 16-byte aligned; on == 0 forces the layer-by-layer kernels.  Both
- * compute the same products and exponentials; q differs only by the order
- * of the softmax row sums (a few ulp). */
+ * W3 are 16-byte aligned; on == 0 (the default) runs the layer-by-layer
+ * kernels.  Both compute the same products and exponentials; q differs only
+ * by the order of the softmax row sums (a few ulp). */
 int arsel_set_mlp_fused(arsel_ctx *ctx, int32_t on);
 
 /* Training state: the network (its W1, W2, W3 are the BF16 copies refreshed by

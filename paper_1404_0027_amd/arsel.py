@@ -228,7 +228,7 @@ def get_schedule(device=None) -> Schedule:
 
 
 def set_mlp_fused(on: bool, device=None) -> None:
-    """Inference forward by the fused kernel (default) or layer by layer."""
+    """Inference forward by the fused kernel or layer by layer (the default)."""
     _check(lib().arsel_set_mlp_fused(context(device), 1 if on else 0), "arsel_set_mlp_fused")
 
 

@@ -41,7 +41,7 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     c->staging = nullptr;
     c->staging_bytes = 0;
     c->staging_event = nullptr;
-    c->mlp_fused = 1;
+    c->mlp_fused = 0;
     c->ws = nullptr;
     c->ws_bytes = 0;
     c->ssa_tab = nullptr;
@@ -54,7 +54,9 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
         tab[2 * (i - kLnTabLo) + 1] = 128.0 / (double)i;
     }
     c->order_split = -1;
-    c->order_blocks = c->order_waves = 0;
+    c->order_items = c->order_large = c->order_waves = 0;
+    c->inst = nullptr;
+    c->inst_bytes = 0;
     if (hipMalloc((void **)&c->queue, 256) != hipSuccess ||
         hipMemset(c->queue, 0, 256) != hipSuccess ||
         hipMalloc((void **)&c->ln_tab, sizeof(tab)) != hipSuccess ||
@@ -82,6 +84,7 @@ extern "C" int arsel_destroy(arsel_ctx *ctx)
     if (ctx->queue) (void)hipFree(ctx->queue);
     if (ctx->order) (void)hipFree(ctx->order);
     if (ctx->order_dev) (void)hipFree(ctx->order_dev);
+    if (ctx->inst) (void)hipFree(ctx->inst);
     for (void *p : ctx->retired) (void)hipFree(p);
     if (ctx->staging_event) {
         (void)hipEventSynchronize(ctx->staging_event);
@@ -126,7 +129,9 @@ extern "C" int arsel_set_schedule(arsel_ctx *ctx, const arsel_schedule *s)
     if (!(bw == 4 || bw == 8 || bw == 16)) return ARSEL_ERR_ARG;
     if (s->wave_max_m < 1 || s->lds_max_m < 0 || s->blocks_per_cu < 1 || s->blocks_per_cu > 8)
         return ARSEL_ERR_ARG;
-    const size_t lds = (size_t)std::max<int64_t>(s->lds_max_m, (int64_t)bw * s->wave_max_m) * sizeof(float);
+    // the pick launch's wavefront slices; the hard piece (at most 16380
+    // floats) is checked with the launch
+    const size_t lds = (size_t)bw * s->wave_max_m * sizeof(float);
     if (lds + 2048 > ctx->lds_per_block) return ARSEL_ERR_ARG;
     ctx->sched = *s;
     return ARSEL_OK;

@@ -28,7 +28,10 @@ struct arsel_ctx {
                                    // arsel_destroy, so graphs captured earlier stay valid
     std::vector<int64_t> order_sizes;   // host sizes the work lists were built from,
     int32_t order_split;                // for this wave_max_m (-1: lists not reusable)
-    uint32_t order_blocks, order_waves; // their lengths
+    uint32_t order_items, order_large, order_waves;   // their lengths (scan items, large
+                                                       // instances, small instances)
+    void *inst;               // per-instance scan accumulators of the uneven-batch call (bit
+    size_t inst_bytes;        // maximum, float sum), zero between calls, grown on demand
     int32_t *staging;         // pinned host staging of the work lists
     size_t staging_bytes;
     hipEvent_t staging_event; // completion of the last staging copy

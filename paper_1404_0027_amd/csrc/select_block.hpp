@@ -1,9 +1,5 @@
-// One instance of the acceptance-rejection selection run by a whole
-// workgroup of NW wavefronts (large M).  Same rule and same random stream as
-// the wavefront version: round r of the workgroup covers trials
-// [128 NW r, 128 NW (r + 1)); wave w takes the 128-trial slice r NW + w and the
-// least accepted trial over the waves wins, so the answer is the sequential
-// rule's for any NW.
+// Workgroup-level pieces of the selection: reductions and scans over the
+// NW wavefronts of a workgroup, and the staged loads of a row piece.
 #pragma once
 
 #include "select_core.hpp"
@@ -80,150 +76,94 @@ __device__ void block_scan(const Acc &A, uint32_t M, float &amax, bool &bad, Blo
     amax = __uint_as_float(mb);
 }
 
-// Least j in [0, n) whose inclusive prefix of F_j = floor(alpha_j 2^shift)
-// exceeds target, or -1 when the n elements sum to at most target.  Thread i
-// owns the contiguous range [i L, (i + 1) L); range sums are read in a skewed
-// order (the sum does not depend on it) so that LDS lanes do not share a bank.
-// `total` returns the sum of the n weights.
-template <int NW, class Acc>
-__device__ int32_t block_prefix_search(const Acc &A, uint32_t n_all, int shift, uint64_t target,
-                                       uint64_t &total, BlockScratch<NW> &bs)
-{
-    constexpr int NT = NW * kWave;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t L = (n_all + NT - 1) / NT;
-    const uint32_t lo = min(tid * L, n_all), hi = min(lo + L, n_all);
-    const uint32_t n = hi - lo;
-    uint64_t part = 0;
-    uint32_t idx = n ? tid % n : 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        part += fixed_weight(A(lo + idx), shift);
-        idx = idx + 1 == n ? 0 : idx + 1;
+// Loads of one piece [p0, p0 + n) of a row, n = min(piece, M - p0) (piece a
+// multiple of 4 floats, at most kStreamBatch float4 per thread of NT): an
+// unaligned head of up to 3 elements, nq aligned float4 slots and a tail of
+// up to 3, all issued before any is used.  Wavefront w holds the slots
+// [w W, (w + 1) W), W = ceil(nq / NW) rounded up to 64, lane l of it the slots
+// w W + 64 u + l (each load instruction reads 1 KB contiguous), so the piece
+// splits into ordered wavefront ranges: wave 0 from element 0 (it holds the
+// head), wave w from its first slot (or the tail's start when it has none),
+// the last wave to the end (it holds the tail); a wave's part of the
+// fixed-point sum is the sum over its range.  store() writes the piece to
+// buf[0 .. n) and returns the thread's part of the sum.
+template <int NT>
+struct PieceLoads {
+    static constexpr int NW = NT / kWave;
+    f32x4 v[kStreamBatch];
+    float hx, tx;
+
+    struct Span {
+        uint32_t n, head, nq, W;
+    };
+
+    __device__ __forceinline__ static Span span(const float *row, uint32_t M, uint32_t p0, uint32_t piece)
+    {
+        Span sp;
+        sp.n = min(piece, M - p0);
+        const uint32_t align = (uint32_t)(((16 - ((uintptr_t)(row + p0) & 15)) & 15) >> 2);
+        sp.head = align < sp.n ? align : sp.n;
+        sp.nq = (sp.n - sp.head) >> 2;
+        sp.W = ((sp.nq + NW - 1) / NW + kWave - 1) / kWave * kWave;
+        return sp;
     }
-    uint64_t S = 0;
-    const uint64_t before = block_excl_scan_u64<NW>(part, S, bs);
-    total = S;
-    if (tid == 0) bs.found = -1;
-    __syncthreads();
-    if (n > 0 && before <= target && target < before + part) {
-        uint64_t P = before;
-        for (uint32_t j = lo; j < hi; ++j) {
-            P += fixed_weight(A(j), shift);
-            if (P > target) {
-                bs.found = (int32_t)j;
-                break;
+
+    // first element of wavefront w's range; wave w ends where wave w + 1
+    // begins, the last wave at n
+    __device__ __forceinline__ static uint32_t wave_begin(const Span &sp, uint32_t w)
+    {
+        return w == 0 ? 0u : sp.head + 4 * min(sp.W * w, sp.nq);
+    }
+
+    __device__ __forceinline__ void issue(const float *row, uint32_t M, uint32_t p0, uint32_t piece,
+                                          uint32_t tid)
+    {
+        const Span sp = span(row, M, p0, piece);
+        const float *s4 = row + p0 + sp.head;
+        const uint32_t base = (tid >> 6) * sp.W + (tid & (kWave - 1));
+        const uint32_t end = min((tid >> 6) * sp.W + sp.W, sp.nq);
+#pragma unroll
+        for (int u = 0; u < kStreamBatch; ++u) {
+            const uint32_t i = base + u * kWave;
+            if (i < end) v[u] = load_stream4(s4 + 4 * i);
+        }
+        hx = tid < sp.head ? row[p0 + tid] : 0.0f;
+        const uint32_t t0 = sp.head + 4 * sp.nq, tl = tid - (NT - kWave);
+        tx = tid >= NT - kWave && tl < sp.n - t0 ? row[p0 + t0 + tl] : 0.0f;
+    }
+
+    __device__ __forceinline__ uint64_t store(const float *row, uint32_t M, uint32_t p0, uint32_t piece,
+                                              uint32_t tid, float *buf, int shift) const
+    {
+        const Span sp = span(row, M, p0, piece);
+        const uint32_t base = (tid >> 6) * sp.W + (tid & (kWave - 1));
+        const uint32_t end = min((tid >> 6) * sp.W + sp.W, sp.nq);
+        uint64_t part = 0;
+#pragma unroll
+        for (int u = 0; u < kStreamBatch; ++u) {
+            const uint32_t i = base + u * kWave;
+            if (i < end) {
+                float *d = buf + sp.head + 4 * i;
+                d[0] = v[u].x;
+                d[1] = v[u].y;
+                d[2] = v[u].z;
+                d[3] = v[u].w;
+                part += fixed_weight(v[u].x, shift) + fixed_weight(v[u].y, shift);
+                part += fixed_weight(v[u].z, shift) + fixed_weight(v[u].w, shift);
             }
+            __builtin_amdgcn_sched_barrier(0);   // one slot's temporaries at a time
         }
-    }
-    __syncthreads();
-    const int32_t j = bs.found;
-    __syncthreads();
-    return j;
-}
-
-// Exact fixed-point inverse transform over the block (instance resident in
-// LDS, or any accessor for moderate M).
-template <int NW, class Acc>
-__device__ int32_t block_fallback_pick(const Acc &A, uint32_t M, int shift, const Stream &st,
-                                       BlockScratch<NW> &bs)
-{
-    // S first (the target depends on it), then the search.
-    uint64_t S = 0;
-    for (uint32_t j = threadIdx.x; j < M; j += NW * kWave) S += fixed_weight(A(j), shift);
-    S = block_sum_u64<NW>(S, bs);
-    const Words w = st.block(kFallbackBlock);
-    const uint64_t V = (uint64_t)w.w0 | ((uint64_t)w.w1 << 32);
-    uint64_t tot;
-    return block_prefix_search<NW>(A, M, shift, umul64hi(V, S), tot, bs);
-}
-
-// The same for an instance left in global memory: one streaming pass for S,
-// then the row is copied into LDS piece by piece (coalesced, several loads in
-// flight) until the piece holding the target is found and searched there.
-template <int NW>
-__device__ int32_t block_fallback_global(const float *row, uint32_t M, int shift, const Stream &st,
-                                         float *piece_buf, uint32_t piece, BlockScratch<NW> &bs)
-{
-    constexpr int NT = NW * kWave;
-    const uint64_t S = block_sum_u64<NW>(stream_fixed_sum<NT>(row, M, shift, threadIdx.x), bs);
-    const Words w = st.block(kFallbackBlock);
-    const uint64_t V = (uint64_t)w.w0 | ((uint64_t)w.w1 << 32);
-    const uint64_t target = umul64hi(V, S);
-    uint64_t before = 0;
-    for (uint32_t p0 = 0; p0 < M; p0 += piece) {
-        const uint32_t n = min(piece, M - p0);
-        stream_each<NT>(row + p0, n, threadIdx.x, [&](uint32_t j, float x) { piece_buf[j] = x; });
-        __syncthreads();
-        uint64_t part;
-        const int32_t j = block_prefix_search<NW>(ContigAcc{piece_buf}, n, shift, target - before, part, bs);
-        if (j >= 0) return (int32_t)p0 + j;
-        before += part;
-    }
-    return -1;   // unreachable for S > 0
-}
-
-// The whole selection for one instance.  maxbits_hint: the block-wide bit
-// maximum from a fused load pass (certifies validity when < 0x7F800000), or
-// 0xFFFFFFFF when no such pass ran.
-//
-// global_row: the instance's row in global memory when A reads it there (no
-// LDS copy); its fallback and alpha0 passes then stream the row and stage it
-// piece by piece in piece_buf (piece floats).  Null when A reads LDS.
-template <int NW, class Acc>
-__device__ Outcome block_select(const Acc &A, uint32_t M, uint32_t maxbits_hint, const Stream &st,
-                                uint32_t t_max, bool want_alpha0, BlockScratch<NW> &bs,
-                                const float *global_row = nullptr, float *piece_buf = nullptr,
-                                uint32_t piece = 0)
-{
-    const int wave = threadIdx.x >> 6;
-    float amax;
-    bool bad;
-    if (maxbits_hint < 0x7F800000u) {
-        amax = __uint_as_float(maxbits_hint);
-        bad = false;
-    } else {
-        block_scan<NW>(A, M, amax, bad, bs);
-    }
-    Outcome o;
-    float env = 0.0f;
-    if (decide_status(true, bad, amax, nullptr, 0u, env, o)) return o;
-    const int L = ceil_log2_u32(M);
-    const int shift = 63 - L - exponent_above(amax);
-    if (want_alpha0) {
-        uint64_t s = 0;
-        if (global_row)
-            s = stream_fixed_sum<NW * kWave>(global_row, M, shift, threadIdx.x);
-        else
-            for (uint32_t j = threadIdx.x; j < M; j += NW * kWave) s += fixed_weight(A(j), shift);
-        o.alpha0 = fixed_to_float(block_sum_u64<NW>(s, bs), shift);
-    }
-    const uint32_t thresh = lemire_threshold(M);
-    const double envd = (double)env;
-    const uint32_t wrounds = (uint32_t)(((uint64_t)t_max + kRoundTrials - 1) / kRoundTrials);
-    for (uint32_t r0 = 0; r0 < wrounds; r0 += NW) {
-        if (threadIdx.x == 0) bs.key = kNoAccept;
-        __syncthreads();
-        const uint32_t r = r0 + (uint32_t)wave;
-        if (r < wrounds) {
-            const uint64_t key = wave_round(A, M, thresh, envd, st, r, t_max);
-            if (key != kNoAccept && lane_id() == 0)
-                atomicMin((unsigned long long *)&bs.key, (unsigned long long)key);
+        if (tid < sp.head) {
+            buf[tid] = hx;
+            part += fixed_weight(hx, shift);
         }
-        __syncthreads();
-        const uint64_t key = bs.key;
-        __syncthreads();
-        if (key != kNoAccept) {
-            o.index = (int32_t)(uint32_t)key;
-            o.trials = (uint32_t)(key >> 32) + 1;
-            return o;
+        const uint32_t t0 = sp.head + 4 * sp.nq, tl = tid - (NT - kWave);
+        if (tid >= NT - kWave && tl < sp.n - t0) {
+            buf[t0 + tl] = tx;
+            part += fixed_weight(tx, shift);
         }
+        return part;
     }
-    if (global_row && piece_buf && piece > 0)
-        o.index = block_fallback_global<NW>(global_row, M, shift, st, piece_buf, piece, bs);
-    else
-        o.index = block_fallback_pick<NW>(A, M, shift, st, bs);
-    o.trials = t_max + 1;
-    return o;
-}
+};
 
 }  // namespace arsel

@@ -8,8 +8,9 @@ def test_ragged_candidates_fit_lds():
         assert cands
         for wave_max_m, bw, lds_max_m, bpc in cands:
             assert bw in (4, 8, 16) and 1 <= bpc <= 8
-            need = max(lds_max_m, bw * wave_max_m) * 4 + 2048
+            need = bw * wave_max_m * 4 + 2048
             assert need <= lds and need * bpc <= 160 * 1024
+            assert lds_max_m in (0, 4096, 8192)
 
 
 def test_signature_is_stable():

@@ -132,7 +132,7 @@ def test_mlp_forward_fused_matches_layer_by_layer(net_and_data, R):
         arsel.set_mlp_fused(True)
         Qf, qf = lp.forward(Xs, As, want_q=True)
     finally:
-        arsel.set_mlp_fused(True)
+        arsel.set_mlp_fused(False)
     qu, qf = qu.cpu().numpy(), qf.cpu().numpy()
     assert np.array_equal(qu > 0, qf > 0)
     assert np.all(np.abs(qf - qu) <= 1e-6 * qu + 1e-12)

@@ -1,5 +1,5 @@
-"""GPU parity of arsel_select_ragged (uneven batches, persistent launch)
-against the CPU oracle, bit for bit, under several schedules."""
+"""GPU parity of arsel_select_ragged (uneven batches) against the CPU oracle,
+bit for bit, under several schedules."""
 import numpy as np
 import pytest
 import torch
@@ -67,16 +67,24 @@ def test_ragged_fallbacks(gpu, t_max):
         assert np.all((g[2] <= 2) | (g[0] < 0)) and np.any(g[2] == 2)
 
 
-@pytest.mark.parametrize("sched", [(64, 8, 0, 2), (256, 4, 2048, 1)])
-def test_ragged_global_fallback_in_pieces(gpu, restore_schedule, sched):
-    """Instances left in global memory take the fallback by staging the row
-    piece by piece (pieces of max(lds_max_m, waves x wave_max_m) floats, so
-    many pieces per instance here); alpha0 is streamed from global memory."""
+@pytest.mark.parametrize("sched", [(64, 8, 0, 2), (256, 4, 2048, 1), (1024, 16, 8192, 1)])
+def test_ragged_hard_chunks_and_fallbacks(gpu, restore_schedule, sched):
+    """Heavy-tailed rows (lognormal, sigma 3) are hard: they are cut into chunks
+    of the schedule's piece (2048 floats: up to 32 chunks per row), each chunk
+    tests every trial whose candidate it holds, and tiny budgets send most of
+    them to the fallback, located from the per-wavefront chunk sums."""
     arsel.set_schedule(arsel.Schedule(*sched))
-    rb = workloads.ragged_mix(K=60, seed=8, log2_lo=10, log2_hi=16)
-    for t_max in (0, 3):
-        g, o = _ragged_both(rb.alpha, rb.offsets, seed=6, step=t_max, t_max=t_max)
-        assert_same(g, o, f"schedule {sched} t_max {t_max}")
+    rng = np.random.default_rng(8)
+    sizes = np.round(2 ** rng.uniform(10, 16, 60)).astype(np.int64)
+    offsets = np.zeros(61, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    alpha = rng.lognormal(0.0, 3.0, int(offsets[-1])).astype(np.float32)
+    for host in (True, False):
+        for t_max in (0, 3, 4096):
+            g, o = _ragged_both(alpha, offsets, seed=6, step=t_max, t_max=t_max, host=host)
+            assert_same(g, o, f"schedule {sched} t_max {t_max} host={host}")
+    if t_max == 4096:
+        assert np.any(g[2] == 4097)          # some rows still fell back
 
 
 def test_ragged_edge_instances(gpu):
@@ -194,8 +202,8 @@ def test_ragged_work_lists_reused_only_for_equal_sizes(gpu):
 
 def test_ragged_counters_cleared_between_calls(gpu):
     """Thirty calls in a row on one stream, outputs pre-filled with a sentinel:
-    every call covers every instance (the kernel's last workgroup clears the
-    list counters for the next one)."""
+    every call covers every instance (each call's scan kernel zeroes the
+    counters its split kernel fills)."""
     alpha, offsets = _sized_batch(4)
     a = torch.from_numpy(alpha).cuda()
     off = torch.from_numpy(offsets).cuda()
@@ -260,6 +268,33 @@ def test_ragged_graph_capture_replays_match_eager(gpu):
     assert_same(g_, o_, "after the replays")
     g_, o_ = _ragged_both(A[0], A[1], seed=2, step=5, host=False)
     assert_same(g_, o_, "device lists after the replays")
+
+
+@pytest.mark.parametrize("sched", [(1024, 8, 8192, 2), (256, 4, 0, 4), (2048, 16, 16384, 1)])
+def test_ragged_sub_batch_and_chunked_rows(gpu, restore_schedule, sched):
+    """A batch whose offsets start inside alpha (offsets[0] > 0, odd sizes, so
+    rows and chunks start at every alignment) with rows of up to 2^17
+    elements, cut into several chunks by every schedule: host and device
+    lists against the oracle."""
+    r = np.random.default_rng(41)
+    K = 160
+    sizes = np.round(2 ** r.uniform(0, 17, K)).astype(np.int64)
+    sizes[[3, 50]] = [131071, 70001]                 # many chunks, odd lengths
+    offsets = np.zeros(K + 1, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    offsets += 37                                      # the batch starts inside alpha
+    fam = r.integers(0, 3, K)
+    alpha = np.empty(int(offsets[-1]) + 5, np.float32)
+    alpha[:37] = np.nan                                # never read
+    for k in range(K):
+        m = int(sizes[k])
+        v = [1.0 - r.random(m), r.exponential(1.0, m), r.lognormal(0.0, 3.0, m)][fam[k]]
+        alpha[offsets[k]:offsets[k + 1]] = v
+    alpha[-5:] = np.nan
+    arsel.set_schedule(arsel.Schedule(*sched))
+    for host in (True, False):
+        g, o = _ragged_both(alpha, offsets, seed=4, step=2, host=host)
+        assert_same(g, o, f"schedule {sched} host={host}")
 
 
 def test_ragged_device_lists_large_batch(gpu):

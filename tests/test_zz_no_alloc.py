@@ -61,6 +61,28 @@ def test_noalloc_fallback_and_edge_sizes(gpu):
         assert np.all(got[0][[0, 17, 200]] == -1)
 
 
+def test_noalloc_hard_rows_in_pieces(gpu):
+    """Heavy-tailed rows up to 65536 elements are hard; here each is one chunk
+    tested piece by piece (pieces of 2048 floats), with budgets that send
+    most of them to the fallback."""
+    s0 = arsel.get_schedule()
+    try:
+        arsel.set_schedule(arsel.Schedule(256, 8, 2048, 1))
+        rng = np.random.default_rng(74)
+        sizes = np.round(2 ** rng.uniform(9, 16, 80)).astype(np.int64)
+        off = np.zeros(81, np.int64)
+        np.cumsum(sizes, out=off[1:])
+        alpha = rng.lognormal(0.0, 3.0, int(off[-1])).astype(np.float32)
+        rb = workloads.RaggedBatch(alpha=alpha, offsets=off, family=np.full(80, 2, np.int8))
+        for t_max in (0, 3, 4096):
+            got, ref = _both(rb, seed=9, step=t_max, t_max=t_max)
+            _check(got, ref, f"t_max={t_max}")
+            o = oracle.select_ragged(alpha, off, seed=9, step=t_max, t_max=t_max, threads=8)
+            assert_same(got, o, f"t_max={t_max} vs oracle")
+    finally:
+        arsel.set_schedule(s0)
+
+
 def test_noalloc_rejects_oversized_batch(gpu):
     K = arsel.RAGGED_NOALLOC_MAX_K + 1
     a = torch.ones(K, dtype=torch.float32, device="cuda")
