@@ -135,6 +135,8 @@ def bench_ragged(torch, arsel, workloads, reps: int = 20):
             "algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / (t * 1e-6) / 1e9, 1),
             "frac_of_8TBs": round(nbytes / (t * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             "us_device_lists": round(us["device_lists"], 2), "us_noalloc": round(us["noalloc"], 2),
+            "traffic_bytes_per_launch": {"k_ragged_scan": load_traffic("ragged_scan"),
+                                         "k_ragged_hard": load_traffic("ragged_hard")},
             "schedule": dict(zip(("wave_max_m", "block_waves", "lds_max_m", "blocks_per_cu"),
                                  tuned.schedule)),
             "tuner_reps": 5}

@@ -5,6 +5,11 @@
         20 times) so that the FETCH_SIZE / WRITE_SIZE counters can be
         calibrated: factor = true KiB / counter KiB per dispatch.
 
+    python -m paper_1404_0027_amd.profiling ragged [WAVE_MAX_M BLOCK_WAVES LDS_MAX_M BLOCKS_PER_CU]
+        Runs the uneven-batch call 12 times on the benchmark's 10^4-instance
+        batch (host-built work lists, indices only) with the given schedule
+        (default 1024 8 0 4), for kernel traces and counters of its launches.
+
     python -m paper_1404_0027_amd.profiling summarize DB KERNEL_SUBSTR [--pmc]
         Prints per-kernel dispatch count and mean/min/max duration from a
         rocprofv3 kernel-trace database, or mean counter values per dispatch
@@ -31,8 +36,12 @@ COPY_MIB = 64
 
 # sources each profiled kernel is compiled from (its traffic record is void
 # once any of them changes)
+_RAGGED_SOURCES = ("select_ragged.hip", "select_block.hpp", "select_core.hpp", "wave_reduce.hpp",
+                   "device.hpp", "launch.hpp")
 KERNEL_SOURCES = {
     "select_tile": ("select_dense.hip", "select_core.hpp", "device.hpp", "launch.hpp"),
+    "ragged_scan": _RAGGED_SOURCES,
+    "ragged_hard": _RAGGED_SOURCES,
 }
 
 
@@ -58,6 +67,24 @@ def copy_probe() -> None:
         b.copy_(a)
     torch.cuda.synchronize()
     print(f"copy probe: 20 x {COPY_MIB} MiB device-to-device copies done", flush=True)
+
+
+def ragged_probe(sched=(1024, 8, 0, 4)) -> None:
+    import torch
+
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_1404_0027_amd import arsel, workloads
+
+    rb = workloads.ragged_mix(K=10000, seed=3)
+    a = torch.from_numpy(rb.alpha).cuda()
+    off = torch.from_numpy(rb.offsets).cuda()
+    idx = torch.empty(rb.K, dtype=torch.int32, device="cuda")
+    arsel.set_schedule(arsel.Schedule(*sched))
+    for s in range(12):
+        arsel.select_ragged(a, off, seed=1, step=s, host_offsets=rb.offsets, index=idx)
+    torch.cuda.synchronize()
+    print(f"ragged probe: 12 calls, K={rb.K}, {4 * int(rb.offsets[-1])} B of propensities, "
+          f"schedule {tuple(sched)}", flush=True)
 
 
 def _kernel_rows(db: str, substr: str):
@@ -117,6 +144,8 @@ def main(argv: list[str]) -> int:
         return 2
     if argv[0] == "copy":
         copy_probe()
+    elif argv[0] == "ragged":
+        ragged_probe(tuple(int(x) for x in argv[1:5]) if len(argv) >= 5 else (1024, 8, 0, 4))
     elif argv[0] == "summarize":
         print(summarize(argv[1], argv[2], pmc="--pmc" in argv))
     elif argv[0] == "traffic":
