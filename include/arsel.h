@@ -133,14 +133,15 @@ int arsel_set_trial_lanes(arsel_ctx *ctx, int32_t lanes);
  * speed and no candidate costs a DRAM access of its own), and the others run
  * their trials by one wavefront each.  Four launches per call: scan, split,
  * chunks, pick.  With host_sizes the work lists are built on the host,
- * otherwise on the device (one extra small kernel per call; for K above
- * 65536 the device lists are in arbitrary order).  M_k == 0 reports -1.
+ * otherwise on the device (three more small launches per call: per-class
+ * counts, then placement; the same longest-first order for any K).
+ * M_k == 0 reports -1.
  * Results are bit-identical to arsel_select on each instance with instance
  * id k, whatever the schedule, order or split.
  * The context holds this call's work lists and counters: calls on one context
  * must not overlap (issue them on one stream).  A call whose host_sizes and
  * schedule split equal the previous host-sized call's reuses the lists already
- * on the device and launches one kernel; otherwise the lists are rebuilt and
+ * on the device and makes only the four launches; otherwise the lists are rebuilt and
  * copied through pinned memory.
  * Graph capture: while `stream` captures, host_sizes is ignored and the lists
  * are built on the device inside the graph, so a replay reads no list that a
@@ -159,12 +160,12 @@ int arsel_select_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offse
  * the work lists built on the device (as with host_sizes NULL), whose lists,
  * counters, keys and per-instance accumulators live in a static device array
  * of the library instead of the context.  The call makes no allocation of
- * any kind (no hipMalloc, hipFree, pinned host memory or copies) and launches
- * five kernels.  The array holds the state of at most 65536 instances (about
- * 9.2 MB); each GPU the library runs on holds its own copy until the process
- * ends.  Each large instance is scanned in at most two items and a hard one
- * is one chunk, so a hard row is tested by one workgroup piece by piece
- * (slower than arsel_select_ragged for batches of few large rows).
+ * any kind (no hipMalloc, hipFree, pinned host memory or copies) and makes
+ * seven launches.  The array holds the state of at most 65536 instances and
+ * fixed pools of 2^18 scan items and 2^16 hard chunks (about 12.3 MB); each
+ * GPU the library runs on holds its own copy until the process ends.  The
+ * chunk plans take the pools' share per instance (up to 32 chunks each), so
+ * batches of many instances have longer chunks than arsel_select_ragged.
  * K > 65536: ARSEL_ERR_SIZE; the array's address could not be found when the
  * context was created: ARSEL_ERR_HIP.  Other arguments and results as
  * arsel_select_ragged (bit-identical for any schedule).  Every call on one

@@ -57,8 +57,8 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     c->order_items = c->order_large = c->order_waves = 0;
     c->inst = nullptr;
     c->inst_bytes = 0;
-    if (hipMalloc((void **)&c->queue, 256) != hipSuccess ||
-        hipMemset(c->queue, 0, 256) != hipSuccess ||
+    if (hipMalloc((void **)&c->queue, kQueueBytes) != hipSuccess ||
+        hipMemset(c->queue, 0, kQueueBytes) != hipSuccess ||
         hipMalloc((void **)&c->ln_tab, sizeof(tab)) != hipSuccess ||
         hipMemcpy(c->ln_tab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess) {
         if (c->queue) (void)hipFree(c->queue);

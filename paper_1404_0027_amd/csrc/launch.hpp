@@ -9,6 +9,9 @@
 
 #include "../../include/arsel.h"
 
+// Bytes of the context's queue word array.
+constexpr size_t kQueueBytes = 2048;
+
 struct arsel_ctx {
     int device;
     int num_cu;
@@ -18,8 +21,8 @@ struct arsel_ctx {
     int dense_waves;          // wavefronts per dense workgroup (4, 8, 16; 0: automatic)
     int trial_lanes;          // lanes per instance of the broadcast kernel (0: automatic)
     arsel_schedule sched;     // ragged schedule
-    uint32_t *queue;          // device counters of the persistent ragged kernel, zero
-                              // between calls (the kernel's last workgroup clears them)
+    uint32_t *queue;          // kQueueBytes of device counters of the uneven-batch call (list
+                              // lengths, per-class histograms of the device-built lists)
     int32_t *order;           // host-built work lists of the ragged kernel (reused while the
     size_t order_bytes;       // sizes repeat), grown on demand
     int32_t *order_dev;       // device-built work lists (rebuilt by every call that uses

@@ -110,87 +110,116 @@ enum : int {
     kQWords = 6
 };
 
-// Device-side lists, ordered longest first by size class (a counting sort in
-// one workgroup), for batches of at most kOrderMaxK instances: the small list
-// (instance ids), the large list (instance ids) and the scan items of the
-// large instances.  It sets every counter of the launches that follow.
-constexpr int32_t kOrderMaxK = 1 << 16;
-constexpr int kOrderThreads = 1024;
+// Device-built lists, ordered longest first by size class like the host
+// ones, for any K, in three launches: k_list_clear zeroes the per-class
+// histograms and cursors in the queue words, k_list_count adds each block's
+// histograms to them, and k_list_scatter places each instance at its class's
+// start (from the histograms) plus its block's share of the class (one global
+// atomic per block and non-empty class) plus its rank in the block.  The
+// order within a class depends on the atomics; nothing downstream depends on
+// that order.  k_list_scatter also sets the list lengths.
+constexpr int kListThreads = 256;
+constexpr int kClasses = 64;
+enum : int {
+    kQHist = 64,                          // [3][64] counts: small, large, scan items
+    kQCursor = kQHist + 3 * kClasses,     // [3][64] next free slot per class
+    kQueueWordsAll = kQCursor + 3 * kClasses
+};
 
-__global__ __launch_bounds__(kOrderThreads) void k_ragged_order(const int64_t *offsets, int32_t K,
-                                                                int32_t wave_max_m, int32_t maxch,
-                                                                int32_t *small, int32_t *large,
-                                                                RScan *items, uint32_t *queue)
+__global__ void k_list_clear(uint32_t *queue)
 {
-    __shared__ uint32_t cnt_s[64], pos_s[64];      // small list, by class
-    __shared__ uint32_t cnt_l[64], pos_l[64];      // large list, by class
-    __shared__ uint32_t cnt_i[64], pos_i[64];      // scan items, by class
-    const int tid = threadIdx.x;
-    const int64_t base = offsets[0];
-    if (tid < 64) cnt_s[tid] = cnt_l[tid] = cnt_i[tid] = 0;
+    for (int i = threadIdx.x; i < kQueueWordsAll; i += blockDim.x) queue[i] = 0;
+}
+
+__global__ __launch_bounds__(kListThreads) void k_list_count(const int64_t *offsets, int32_t K,
+                                                             int32_t wave_max_m, int32_t maxch,
+                                                             uint32_t *queue)
+{
+    __shared__ uint32_t h[3 * kClasses];
+    const int t = threadIdx.x;
+    for (int i = t; i < 3 * kClasses; i += kListThreads) h[i] = 0;
     __syncthreads();
-    for (int k = tid; k < K; k += kOrderThreads) {
-        const int64_t m = offsets[k + 1] - offsets[k];
+    const int64_t k = (int64_t)blockIdx.x * kListThreads + t;
+    if (k < K) {
+        const int64_t base = offsets[0];
+        const int64_t o0 = offsets[k];
+        const int64_t m = offsets[k + 1] - o0;
         const int c = size_class(m);
         if (m <= wave_max_m || bad_size(m)) {
-            atomicAdd(&cnt_s[c], 1u);
+            atomicAdd(&h[c], 1u);
         } else {
-            atomicAdd(&cnt_l[c], 1u);
-            atomicAdd(&cnt_i[c], (uint32_t)chunk_plan(offsets[k] - base, m, maxch).nch);
+            atomicAdd(&h[kClasses + c], 1u);
+            atomicAdd(&h[2 * kClasses + c], (uint32_t)chunk_plan(o0 - base, m, maxch).nch);
         }
     }
     __syncthreads();
-    if (tid < 3) {
-        uint32_t *cnt = tid == 0 ? cnt_s : tid == 1 ? cnt_l : cnt_i;
-        uint32_t *pos = tid == 0 ? pos_s : tid == 1 ? pos_l : pos_i;
+    for (int i = t; i < 3 * kClasses; i += kListThreads)
+        if (h[i]) atomicAdd(&queue[kQHist + i], h[i]);
+}
+
+__global__ __launch_bounds__(kListThreads) void k_list_scatter(const int64_t *offsets, int32_t K,
+                                                               int32_t wave_max_m, int32_t maxch,
+                                                               int32_t *small, int32_t *large,
+                                                               RScan *items, uint32_t *queue)
+{
+    __shared__ uint32_t start[3 * kClasses];   // first position of each class in its list
+    __shared__ uint32_t loc[3 * kClasses];     // this block's count, then its base, per class
+    const int t = threadIdx.x;
+    for (int i = t; i < 3 * kClasses; i += kListThreads) {
+        start[i] = queue[kQHist + i];
+        loc[i] = 0;
+    }
+    __syncthreads();
+    if (t < 3) {
         uint32_t run = 0;
-        for (int b = 63; b >= 0; --b) {
-            pos[b] = run;
-            run += cnt[b];
+        for (int b = kClasses - 1; b >= 0; --b) {
+            const uint32_t n = start[t * kClasses + b];
+            start[t * kClasses + b] = run;
+            run += n;
         }
-        if (tid == 0) queue[kQNSmall] = run;
-        if (tid == 1) queue[kQNLarge] = run;
-        if (tid == 2) queue[kQNItems] = run;
+        if (blockIdx.x == 0) queue[t == 0 ? kQNSmall : t == 1 ? kQNLarge : kQNItems] = run;
     }
     __syncthreads();
-    for (int k = tid; k < K; k += kOrderThreads) {
-        const int64_t off = offsets[k] - base;
-        const int64_t m = offsets[k + 1] - offsets[k];
-        const int c = size_class(m);
-        if (m <= wave_max_m || bad_size(m)) {
-            small[atomicAdd(&pos_s[c], 1u)] = k;
+    const int64_t k = (int64_t)blockIdx.x * kListThreads + t;
+    const bool in = k < K;
+    int c = 0;
+    bool sm = false;
+    uint32_t r = 0, ri = 0;
+    int64_t off = 0, m = 0;
+    ChunkPlan p{0, 0, 0};
+    if (in) {
+        const int64_t o0 = offsets[k];
+        m = offsets[k + 1] - o0;
+        off = o0 - offsets[0];
+        c = size_class(m);
+        sm = m <= wave_max_m || bad_size(m);
+        if (sm) {
+            r = atomicAdd(&loc[c], 1u);
         } else {
-            large[atomicAdd(&pos_l[c], 1u)] = k;
-            const ChunkPlan p = chunk_plan(off, m, maxch);
-            const uint32_t q = atomicAdd(&pos_i[c], (uint32_t)p.nch);
-            for (int32_t ch = 0; ch < p.nch; ++ch) items[q + ch] = chunk_item(p, off, m, k, ch);
+            p = chunk_plan(off, m, maxch);
+            r = atomicAdd(&loc[kClasses + c], 1u);
+            ri = atomicAdd(&loc[2 * kClasses + c], (uint32_t)p.nch);
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < 3 * kClasses; i += kListThreads)
+        if (loc[i]) loc[i] = atomicAdd(&queue[kQCursor + i], loc[i]);
+    __syncthreads();
+    if (in) {
+        if (sm) {
+            small[start[c] + loc[c] + r] = (int32_t)k;
+        } else {
+            large[start[kClasses + c] + loc[kClasses + c] + r] = (int32_t)k;
+            const uint32_t q = start[2 * kClasses + c] + loc[2 * kClasses + c] + ri;
+            for (int32_t ch = 0; ch < p.nch; ++ch) items[q + ch] = chunk_item(p, off, m, (int32_t)k, ch);
         }
     }
 }
 
-// Larger device-built batches: the counters first (zero), then the unordered
-// split (k_ragged_classify).
+// The counters only (the error path of a call).
 __global__ void k_ragged_reset(uint32_t *queue)
 {
     if (threadIdx.x < kQWords) queue[threadIdx.x] = 0;
-}
-
-__global__ void k_ragged_classify(const int64_t *offsets, int32_t K, int32_t wave_max_m,
-                                  int32_t maxch, int32_t *small, int32_t *large, RScan *items,
-                                  uint32_t *queue)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    const int64_t m = offsets[k + 1] - offsets[k];
-    if (m <= wave_max_m || bad_size(m)) {
-        small[atomicAdd(&queue[kQNSmall], 1u)] = k;
-    } else {
-        large[atomicAdd(&queue[kQNLarge], 1u)] = k;
-        const int64_t off = offsets[k] - offsets[0];
-        const ChunkPlan p = chunk_plan(off, m, maxch);
-        const uint32_t q = atomicAdd(&queue[kQNItems], (uint32_t)p.nch);
-        for (int32_t ch = 0; ch < p.nch; ++ch) items[q + ch] = chunk_item(p, off, m, k, ch);
-    }
 }
 
 __global__ void k_ragged_clear(uint32_t *p, int64_t n)
@@ -520,6 +549,8 @@ __global__ __launch_bounds__(kHardThreads, 4) void k_ragged_hard(const float *al
     if (tid == 0) bs.key = kNoAccept;
     uint64_t part = 0;
     uint64_t kb = kNoAccept;   // least accepted (trial << 32 | j) of this thread in the chunk
+    uint32_t held = 0xFFFFFFFFu;   // round whose draws the registers hold
+    uint32_t ja[kHardPer], jb[kHardPer], ua[kHardPer], ub[kHardPer];
     for (;;) {
         const uint32_t n = min(piece, cur.ce - p0);
         const bool last_piece = p0 + piece >= cur.ce;
@@ -540,8 +571,8 @@ __global__ __launch_bounds__(kHardThreads, 4) void k_ragged_hard(const float *al
         const double envs = (double)amax * 0x1p-32;
         const uint32_t thresh = lemire_threshold(cur.M);
         const Stream st = make_stream(seed, step, (uint32_t)cur.k, kTagUniform);
-        uint32_t ja[kHardPer], jb[kHardPer], ua[kHardPer], ub[kHardPer];
         auto draw = [&](uint32_t round) {
+            held = round;
 #pragma unroll
             for (int q = 0; q < kHardPer; ++q) {
                 const uint32_t b = round * (NT * kHardPer) + tid + NT * q;
@@ -559,7 +590,8 @@ __global__ __launch_bounds__(kHardThreads, 4) void k_ragged_hard(const float *al
                 __builtin_amdgcn_sched_barrier(0);
             }
         };
-        draw(0);
+        // a later piece of the same chunk reuses the first round's draws
+        if (p0 == cur.c0 || held != 0) draw(0);
         part += ld.store(cur.row, cur.ce, p0, piece, tid, buf, shift);
         __syncthreads();
         if (have_next) ld.issue(nxt.row, nxt.ce, np0, piece, tid);
@@ -883,7 +915,8 @@ static int hard_blocks_per_cu(uint32_t piece)
 }
 
 // Enqueue scan, split, hard chunks and pick for lists already in place
-// (maxch: the chunk plan of the lists).  On a launch failure after the scan
+// (maxch: the hard chunks' plan, at most maxch chunks per instance, which the
+// list buffer's chunk capacity must allow).  On a launch failure after the scan
 // the accumulators and counters are cleared again, so the next call starts
 // from zero.
 static int run_ragged(arsel_ctx *ctx, const float *alpha, const int64_t *offsets, int32_t K,
@@ -973,31 +1006,33 @@ static int ensure_acc(arsel_ctx *ctx, int32_t K, hipStream_t s)
 static int build_lists_on_device(const int64_t *offsets, int32_t K, int32_t wave_max_m,
                                  int32_t maxch, const ListLayout &l, uint32_t *queue, hipStream_t s)
 {
-    if (K <= kOrderMaxK) {
-        hipLaunchKernelGGL(k_ragged_order, dim3(1), dim3(kOrderThreads), 0, s, offsets, K, wave_max_m,
-                           maxch, l.small, l.large, l.items, queue);
-    } else {
-        hipLaunchKernelGGL(k_ragged_reset, dim3(1), dim3(64), 0, s, queue);
-        if (hipGetLastError() != hipSuccess) return ARSEL_ERR_HIP;
-        hipLaunchKernelGGL(k_ragged_classify, dim3((K + 255) / 256), dim3(256), 0, s, offsets, K,
-                           wave_max_m, maxch, l.small, l.large, l.items, queue);
-    }
+    const unsigned grid = (unsigned)(((int64_t)K + kListThreads - 1) / kListThreads);
+    hipLaunchKernelGGL(k_list_clear, dim3(1), dim3(512), 0, s, queue);
+    if (hipGetLastError() != hipSuccess) return ARSEL_ERR_HIP;
+    hipLaunchKernelGGL(k_list_count, dim3(grid), dim3(kListThreads), 0, s, offsets, K, wave_max_m, maxch, queue);
+    if (hipGetLastError() != hipSuccess) return ARSEL_ERR_HIP;
+    hipLaunchKernelGGL(k_list_scatter, dim3(grid), dim3(kListThreads), 0, s, offsets, K, wave_max_m, maxch,
+                       l.small, l.large, l.items, queue);
     return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
 }
 
 // Scratch of arsel_select_ragged_noalloc: the counters (padded to 256
-// bytes), the lists, keys, scan items (at most two per instance) and hard
-// chunks (at most one per instance) for at most kNoAllocMaxK instances, and
-// the accumulators, in a file-scope device array (about 9.2 MB).  Each GPU the library runs on holds its own copy
+// bytes), the lists and keys of at most kNoAllocMaxK instances, pools of
+// scan items and hard chunks whose share per instance sets the chunk plans
+// (so a batch of 10^4 instances is chunked as finely as with the context's
+// buffers), and the accumulators, in a file-scope device array (about
+// 12.3 MB).  Each GPU the library runs on holds its own copy
 // until the process ends; host code reaches it only through the address
 // hipGetSymbolAddress returns for the current device (ragged_scratch_address).
 // Static storage starts zeroed; every launch leaves the accumulators zero and
 // the ordering and split kernels set the counters, lists and keys.
-constexpr int32_t kNoAllocMaxK = kOrderMaxK;
-constexpr int32_t kNoAllocMaxCh = 1;
-constexpr size_t kNoAllocItems = (size_t)kNoAllocMaxK * (kNoAllocMaxCh + 1);
-constexpr size_t kNoAllocHItems = (size_t)kNoAllocMaxK * kNoAllocMaxCh;
-constexpr size_t kScratchQueueWords = 64;
+constexpr int32_t kNoAllocMaxK = 1 << 16;
+constexpr int32_t kNoAllocItemPool = 1 << 18;   // scan items: K (maxch + 1) <= pool + K
+constexpr int32_t kNoAllocHardPool = 1 << 16;   // hard chunks: K hard_maxch <= pool
+constexpr size_t kNoAllocItems = (size_t)kNoAllocItemPool + kNoAllocMaxK;
+constexpr size_t kNoAllocHItems = (size_t)kNoAllocHardPool;
+constexpr size_t kScratchQueueWords = 512;   // the queue words, 2 KB
+static_assert(kQueueWordsAll <= (int)kScratchQueueWords && kQueueWordsAll * 4 <= (int)kQueueBytes, "queue words");
 constexpr size_t kScratchListWords = 7 * (size_t)kNoAllocMaxK + sizeof(RScan) / 4 * kNoAllocItems +
                                      sizeof(HItem) / 4 * kNoAllocHItems;
 constexpr size_t kScratchWords = kScratchQueueWords + kScratchListWords + 2 * (size_t)kNoAllocMaxK;
@@ -1175,9 +1210,9 @@ extern "C" int arsel_select_ragged_noalloc(arsel_ctx *ctx, const float *alpha,
     int32_t *lists = reinterpret_cast<int32_t *>(queue + kScratchQueueWords);
     RAcc *acc = reinterpret_cast<RAcc *>(queue + kScratchQueueWords + kScratchListWords);
     const ListLayout l = list_layout(lists, K, kNoAllocItems);
-    hipLaunchKernelGGL(k_ragged_order, dim3(1), dim3(kOrderThreads), 0, s, offsets, K,
-                       ctx->sched.wave_max_m, kNoAllocMaxCh, l.small, l.large, l.items, queue);
-    if (hipGetLastError() != hipSuccess) return ARSEL_ERR_HIP;
-    return run_ragged(ctx, alpha, offsets, K, l, kNoAllocMaxCh, queue + kQNItems, 0, queue + kQNLarge, 0,
+    const int32_t maxch = std::min<int32_t>(32, kNoAllocItemPool / K);
+    const int32_t hard_maxch = std::min<int32_t>(32, kNoAllocHardPool / K);
+    if ((rc = build_lists_on_device(offsets, K, ctx->sched.wave_max_m, maxch, l, queue, s))) return rc;
+    return run_ragged(ctx, alpha, offsets, K, l, hard_maxch, queue + kQNItems, 0, queue + kQNLarge, 0,
                       queue + kQNSmall, 0, queue, acc, seed, step, t_max, index, alpha0, trials, s);
 }

@@ -70,12 +70,13 @@ def test_ragged_fallbacks(gpu, t_max):
 @pytest.mark.parametrize("sched", [(64, 8, 0, 2), (256, 4, 2048, 1), (1024, 16, 8192, 1)])
 def test_ragged_hard_chunks_and_fallbacks(gpu, restore_schedule, sched):
     """Heavy-tailed rows (lognormal, sigma 3) are hard: they are cut into chunks
-    of the schedule's piece (2048 floats: up to 32 chunks per row), each chunk
-    tests every trial whose candidate it holds, and tiny budgets send most of
-    them to the fallback, located from the per-wavefront chunk sums."""
+    of the schedule's piece (2048 floats: up to 32 chunks per row on the
+    device-built path, longer rows then take chunks of several pieces), each
+    chunk tests every trial whose candidate it holds, and tiny budgets send
+    most of them to the fallback, located from the chunk sums."""
     arsel.set_schedule(arsel.Schedule(*sched))
     rng = np.random.default_rng(8)
-    sizes = np.round(2 ** rng.uniform(10, 16, 60)).astype(np.int64)
+    sizes = np.round(2 ** rng.uniform(10, 17.5, 60)).astype(np.int64)
     offsets = np.zeros(61, np.int64)
     np.cumsum(sizes, out=offsets[1:])
     alpha = rng.lognormal(0.0, 3.0, int(offsets[-1])).astype(np.float32)

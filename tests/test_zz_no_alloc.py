@@ -62,14 +62,15 @@ def test_noalloc_fallback_and_edge_sizes(gpu):
 
 
 def test_noalloc_hard_rows_in_pieces(gpu):
-    """Heavy-tailed rows up to 65536 elements are hard; here each is one chunk
-    tested piece by piece (pieces of 2048 floats), with budgets that send
-    most of them to the fallback."""
+    """Heavy-tailed rows of up to ~185000 elements are hard; with pieces of
+    2048 floats and at most 32 chunks per row the longest rows' chunks are
+    tested piece by piece, with budgets that send most of them to the
+    fallback."""
     s0 = arsel.get_schedule()
     try:
         arsel.set_schedule(arsel.Schedule(256, 8, 2048, 1))
         rng = np.random.default_rng(74)
-        sizes = np.round(2 ** rng.uniform(9, 16, 80)).astype(np.int64)
+        sizes = np.round(2 ** rng.uniform(9, 17.5, 80)).astype(np.int64)
         off = np.zeros(81, np.int64)
         np.cumsum(sizes, out=off[1:])
         alpha = rng.lognormal(0.0, 3.0, int(off[-1])).astype(np.float32)
