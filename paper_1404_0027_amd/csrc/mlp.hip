@@ -59,12 +59,18 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // One thread's 8-element chunk of a 64 x 32 operand tile.  KC: row t/4,
 // k offset 8 (t % 4); otherwise k row t/8, 8 consecutive m at 8 (t % 8).
-template <bool KC>
+// VEC: every chunk lies wholly inside or wholly outside the operand (16-byte
+// aligned base, ld, K (KC) or rows (otherwise) multiples of 8 and at least
+// 8), so a chunk is one unconditional 16-byte load from a clamped address
+// and a mask (an AND, which the compiler does not turn back into a branch
+// around the load): the compiler can then count the loads and keep those of
+// later steps in flight.
+template <bool KC, bool VEC>
 struct Chunk {
     u32x4 v;
 
     __device__ __forceinline__ void load(const __bf16 *X, int64_t ld, int rows, int K, int r0,
-                                         int k0, bool vec)
+                                         int k0)
     {
         const int t = threadIdx.x;
         union {
@@ -75,8 +81,12 @@ struct Chunk {
             const int r = t >> 2, kk = (t & 3) * 8;
             const int gr = r0 + r, gk = k0 + kk;
             const __bf16 *p = X + (int64_t)gr * ld + gk;
-            if (vec && gr < rows && gk + 8 <= K) {
-                c.u = *reinterpret_cast<const u32x4 *>(p);
+            if (VEC) {
+                // an unconditional load from a valid (clamped) address, then a select
+                const u32x4 x = *reinterpret_cast<const u32x4 *>(X + (int64_t)min(gr, rows - 1) * ld +
+                                                                 min(gk, K - 8));
+                const uint32_t keep = (gr < rows && gk < K) ? 0xFFFFFFFFu : 0u;
+                c.u = x & keep;
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) c.h[e] = (gr < rows && gk + e < K) ? p[e] : (__bf16)0.0f;
@@ -85,8 +95,11 @@ struct Chunk {
             const int kk = t >> 3, rr = (t & 7) * 8;
             const int gk = k0 + kk, gr = r0 + rr;
             const __bf16 *p = X + (int64_t)gk * ld + gr;
-            if (vec && gk < K && gr + 8 <= rows) {
-                c.u = *reinterpret_cast<const u32x4 *>(p);
+            if (VEC) {
+                const u32x4 x = *reinterpret_cast<const u32x4 *>(X + (int64_t)min(gk, K - 1) * ld +
+                                                                 min(gr, rows - 8));
+                const uint32_t keep = (gk < K && gr < rows) ? 0xFFFFFFFFu : 0u;
+                c.u = x & keep;
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) c.h[e] = (gk < K && gr + e < rows) ? p[e] : (__bf16)0.0f;
@@ -114,11 +127,19 @@ struct Chunk {
     }
 };
 
-template <bool A_KC, bool B_KC>
+// The K range is walked in steps of kGK = 64 (two 32-wide chunks per
+// operand).  Each thread holds the chunks of the next ST steps in registers
+// (a ring, refilled as each step is stored), so ST steps of loads are in
+// flight behind the MFMAs (ST = 4 for long K; 1 keeps the registers, and the
+// workgroups per CU, of short-K products); the LDS tiles are double-buffered,
+// so one barrier per step suffices: a thread that stores step t + 1 into the
+// buffer of step t - 1 has passed barrier t, which every thread reaches only
+// after its MFMAs of step t - 1.
+template <bool A_KC, bool B_KC, bool VEC, int ST>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 sA[kGT][kGK + kGPad];
-    __shared__ __attribute__((aligned(16))) __bf16 sB[kGT][kGK + kGPad];
+    __shared__ __attribute__((aligned(16))) __bf16 sA[2][kGT][kGK + kGPad];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][kGT][kGK + kGPad];
     const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -130,46 +151,57 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4m){0.f, 0.f, 0.f, 0.f};
 
-    // the slice's K range, in steps of 64 loaded as two 32-wide chunks per
-    // operand (chunks past ke or K are zero-filled by the loads)
-    const int kend = ke;
-    Chunk<A_KC> ca[2];
-    Chunk<B_KC> cb[2];
-    auto fetch = [&](int k0) {
+    // chunks past ke or K are zero-filled by the loads; the steps are padded
+    // to whole rounds of ST (the padding multiplies zeros), so the stage
+    // loop has no exit and the accumulators stay in place
+    Chunk<A_KC, VEC> ca[ST][2];
+    Chunk<B_KC, VEC> cb[ST][2];
+    const int nround = (ke - kb + ST * kGK - 1) / (ST * kGK);
+    static_assert(ST == 1 || ST % 2 == 0, "the LDS buffer of a step is its parity");
+#pragma unroll
+    for (int st = 0; st < ST; ++st) {
+        const int k0 = kb + st * kGK;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int kk = k0 + 32 * h;
-            ca[h].load(g.A, g.lda, g.M, kend, m0, kk, g.vec_a);
-            cb[h].load(g.B, g.ldb, g.N, kend, n0, kk, g.vec_b);
+            ca[st][h].load(g.A, g.lda, g.M, ke, m0, k0 + 32 * h);
+            cb[st][h].load(g.B, g.ldb, g.N, ke, n0, k0 + 32 * h);
         }
-    };
-    if (kb < ke) fetch(kb);
-    for (int k0 = kb; k0 < ke; k0 += kGK) {
+    }
+    const int rl = lane & 15;
+    for (int rd = 0; rd < nround; ++rd) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            ca[h].store(sA, 32 * h);
-            cb[h].store(sB, 32 * h);
-        }
-        __syncthreads();
-        if (k0 + kGK < ke) fetch(k0 + kGK);
-        const int rl = lane & 15;
+        for (int st = 0; st < ST; ++st) {
+            const int bf = ST == 1 ? (rd & 1) : (st & 1);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int kq = 32 * h + (lane >> 4) * 8;
-            bf16x8 a[2], b[2];
+            for (int h = 0; h < 2; ++h) {
+                ca[st][h].store(sA[bf], 32 * h);
+                cb[st][h].store(sB[bf], 32 * h);
+            }
+            __syncthreads();
+            // the chunks of the step ST later (zero past the end)
+            const int kn = kb + ((rd + 1) * ST + st) * kGK;
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = *reinterpret_cast<const bf16x8 *>(&sA[wm + 16 * i + rl][kq]);
+            for (int h = 0; h < 2; ++h) {
+                ca[st][h].load(g.A, g.lda, g.M, ke, m0, kn + 32 * h);
+                cb[st][h].load(g.B, g.ldb, g.N, ke, n0, kn + 32 * h);
+            }
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                b[j] = *reinterpret_cast<const bf16x8 *>(&sB[wn + 16 * j + rl][kq]);
+            for (int h = 0; h < 2; ++h) {
+                const int kq = 32 * h + (lane >> 4) * 8;
+                bf16x8 a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i)
+                    a[i] = *reinterpret_cast<const bf16x8 *>(&sA[bf][wm + 16 * i + rl][kq]);
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                    b[j] = *reinterpret_cast<const bf16x8 *>(&sB[bf][wn + 16 * j + rl][kq]);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
         }
-        __syncthreads();
     }
     // D layout: lane holds rows 4*(lane/16) + r, column lane % 16 of each 16 x 16 block.
     const bool split = gridDim.z > 1;
@@ -214,6 +246,24 @@ static bool vec_ok(const void *p, int64_t ld)
     return ((uintptr_t)p % 16) == 0 && (ld % 8) == 0;
 }
 
+template <bool A_KC, bool B_KC>
+static void launch_gemm_kc(const GemmArgs &g, bool vec, bool deep, dim3 grid, hipStream_t s)
+{
+    if (vec && deep) hipLaunchKernelGGL((k_gemm<A_KC, B_KC, true, 4>), grid, dim3(256), 0, s, g);
+    else if (vec) hipLaunchKernelGGL((k_gemm<A_KC, B_KC, true, 1>), grid, dim3(256), 0, s, g);
+    else if (deep) hipLaunchKernelGGL((k_gemm<A_KC, B_KC, false, 4>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm<A_KC, B_KC, false, 1>), grid, dim3(256), 0, s, g);
+}
+
+static void launch_gemm(const GemmArgs &g, bool a_kc, bool b_kc, bool vec, bool deep, dim3 grid,
+                        hipStream_t s)
+{
+    if (a_kc && b_kc) launch_gemm_kc<true, true>(g, vec, deep, grid, s);
+    else if (a_kc) launch_gemm_kc<true, false>(g, vec, deep, grid, s);
+    else if (b_kc) launch_gemm_kc<false, true>(g, vec, deep, grid, s);
+    else launch_gemm_kc<false, false>(g, vec, deep, grid, s);
+}
+
 // part: scratch for split-K partials (S * M * ldc floats) or null (no split).
 static int gemm(GemmArgs g, bool a_kc, bool b_kc, hipStream_t s, arsel_ctx *ctx = nullptr,
                 float *part = nullptr, size_t part_floats = 0)
@@ -238,10 +288,12 @@ static int gemm(GemmArgs g, bool a_kc, bool b_kc, hipStream_t s, arsel_ctx *ctx 
         grid.z = S;
         g.C = part;
     }
-    if (a_kc && b_kc) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, s, g);
-    else if (a_kc) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, g);
-    else if (b_kc) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, g);
+    // whole-chunk operands (see Chunk): the K range of every split-K slice
+    // is a multiple of the k step, so K itself decides
+    const bool vec = g.vec_a && g.vec_b && g.K % 8 == 0 && (a_kc || g.M % 8 == 0) &&
+                     (b_kc || g.N % 8 == 0);
+    const bool deep = g.kslice >= 8 * kGK;   // at least two rounds of four steps
+    launch_gemm(g, a_kc, b_kc, vec, deep, grid, s);
     if (S > 1) {
         const int64_t n = (int64_t)g.M * g.N;
         hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, S,
