@@ -264,21 +264,35 @@ __device__ __forceinline__ int ceil_log2_u32(uint32_t n)
     return n <= 1 ? 0 : 32 - __clz((int)(n - 1));
 }
 
-// floor(a * 2^shift) for a >= 0 finite, from the bits of a: a = m * 2^(e-150)
-// with m the 24-bit significand.  The caller guarantees the result < 2^63.
+// floor(a * 2^shift) for a >= 0 finite, from the bits of a: a = m * 2^s' with
+// m the 24-bit significand (implicit bit for normal numbers) and
+// s' = max(e, 1) - 150.  The caller guarantees the result < 2^63.  Branch-free:
+// with s = s' + shift, floor(m 2^s) is (m 2^39) >> (39 - s) for s <= 39 (the
+// right shift drops the fraction; m < 2^24, so a shift of 63 already gives 0)
+// and m << s above; both shift amounts are clamped to [0, 63].
 __device__ __forceinline__ uint64_t fixed_weight(float a, int shift)
 {
     const uint32_t b = __float_as_uint(a);
-    uint32_t e = (b >> 23) & 0xFFu;
-    uint32_t m = b & 0x7FFFFFu;
-    if (e == 0)
-        e = 1;
-    else
-        m |= 0x800000u;
-    const int s = (int)e - 150 + shift;
-    if (m == 0 || s <= -24) return 0;
-    if (s >= 0) return (uint64_t)m << (s > 63 ? 63 : s);
-    return (uint64_t)(m >> (-s));
+    const uint32_t e = (b >> 23) & 0xFFu;
+    const uint32_t m = (b & 0x7FFFFFu) | (min(e, 1u) << 23);
+    const int s = (int)max(e, 1u) - 150 + shift;
+    const uint32_t r = (uint32_t)min(max(39 - s, 0), 63);
+    const uint32_t t = (uint32_t)min(max(s, 0), 63);
+    const uint64_t lo = ((uint64_t)m << 39) >> r;
+    const uint64_t hi = (uint64_t)m << t;
+    return s > 39 ? hi : lo;
+}
+
+// fixed_weight when s <= 39 is known: a <= alpha_max with alpha_max a normal
+// float and shift = 63 - L - E chosen from alpha_max (2^(E-1) <= alpha_max <
+// 2^E) give s <= 39 - L.
+__device__ __forceinline__ uint64_t fixed_weight_le39(float a, int shift)
+{
+    const uint32_t b = __float_as_uint(a);
+    const uint32_t e = (b >> 23) & 0xFFu;
+    const uint32_t m = (b & 0x7FFFFFu) | (min(e, 1u) << 23);
+    const int s = (int)max(e, 1u) - 150 + shift;
+    return ((uint64_t)m << 39) >> (uint32_t)min(39 - s, 63);
 }
 
 // (float)S rounded to nearest even, then scaled by 2^-shift with one more

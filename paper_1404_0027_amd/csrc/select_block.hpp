@@ -132,9 +132,13 @@ struct PieceLoads {
         tx = tid >= NT - kWave && tl < sp.n - t0 ? row[p0 + t0 + tl] : 0.0f;
     }
 
+    // LE39: every element's fixed-point exponent is at most 39 (see
+    // fixed_weight_le39), true when the row's maximum is a normal float.
+    template <bool LE39>
     __device__ __forceinline__ uint64_t store(const float *row, uint32_t M, uint32_t p0, uint32_t piece,
                                               uint32_t tid, float *buf, int shift) const
     {
+        auto fw = [shift](float x) { return LE39 ? fixed_weight_le39(x, shift) : fixed_weight(x, shift); };
         const Span sp = span(row, M, p0, piece);
         const uint32_t base = (tid >> 6) * sp.W + (tid & (kWave - 1));
         const uint32_t end = min((tid >> 6) * sp.W + sp.W, sp.nq);
@@ -148,19 +152,19 @@ struct PieceLoads {
                 d[1] = v[u].y;
                 d[2] = v[u].z;
                 d[3] = v[u].w;
-                part += fixed_weight(v[u].x, shift) + fixed_weight(v[u].y, shift);
-                part += fixed_weight(v[u].z, shift) + fixed_weight(v[u].w, shift);
+                part += fw(v[u].x) + fw(v[u].y);
+                part += fw(v[u].z) + fw(v[u].w);
             }
             __builtin_amdgcn_sched_barrier(0);   // one slot's temporaries at a time
         }
         if (tid < sp.head) {
             buf[tid] = hx;
-            part += fixed_weight(hx, shift);
+            part += fw(hx);
         }
         const uint32_t t0 = sp.head + 4 * sp.nq, tl = tid - (NT - kWave);
         if (tid >= NT - kWave && tl < sp.n - t0) {
             buf[t0 + tl] = tx;
-            part += fixed_weight(tx, shift);
+            part += fw(tx);
         }
         return part;
     }

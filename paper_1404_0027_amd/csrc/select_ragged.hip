@@ -430,8 +430,9 @@ __host__ __device__ inline uint32_t hard_chunk_len(int64_t m, int32_t maxch, uin
 // Hard / easy split of the large instances by the expected number of trials
 // M alpha_max / alpha_0 (estimated).  Hard instance at position p of its list
 // owns chunks hc[p] .. hc[p] + ceil(M / L) - 1, and its slot in `best` is
-// reset.  Rows whose scan found an invalid value or no positive sum go to the
-// easy list, whose wavefront path validates the row itself.  Positions come
+// reset.  Rows whose scan found an invalid value, no positive sum or a
+// subnormal maximum go to the easy list, whose wavefront path validates the
+// row itself.  Positions come
 // from one atomic per wavefront and counter (the counters start at zero), so
 // the lists are in no particular order.
 constexpr int kSplitThreads = 256;
@@ -458,7 +459,9 @@ __global__ __launch_bounds__(kSplitThreads) void k_ragged_split(const int64_t *o
         const RAcc a = acc[k];
         const int64_t m = offsets[k + 1] - offsets[k];
         const float amax = __uint_as_float(a.maxbits);
-        const bool valid = a.maxbits < 0x7F800000u && a.sum > 0.0f;
+        // a hard row needs a normal maximum (its chunks take the cheaper exact
+        // weight); a subnormal one, like an invalid row, goes to the easy list
+        const bool valid = a.maxbits >= 0x00800000u && a.maxbits < 0x7F800000u && a.sum > 0.0f;
         is_hard = valid && (float)m * amax > (float)kHardTrials * a.sum;
         if (is_hard) {
             const uint32_t L = hard_chunk_len(m, maxch, piece);
@@ -592,7 +595,9 @@ __global__ __launch_bounds__(kHardThreads, 4) void k_ragged_hard(const float *al
         };
         // a later piece of the same chunk reuses the first round's draws
         if (p0 == cur.c0 || held != 0) draw(0);
-        part += ld.store(cur.row, cur.ce, p0, piece, tid, buf, shift);
+        // hard rows have a normal maximum (the split's rule), so every weight
+        // has s <= 39
+        part += ld.template store<true>(cur.row, cur.ce, p0, piece, tid, buf, shift);
         __syncthreads();
         if (have_next) ld.issue(nxt.row, nxt.ce, np0, piece, tid);
         for (uint32_t round = 0;;) {
