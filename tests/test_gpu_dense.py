@@ -65,6 +65,19 @@ def test_large_m_global_path(gpu, layout):
     assert_same(g, o, f"global layout {layout}")
 
 
+def test_very_large_m(gpu):
+    """Two instances of 2^24 + 7 reactions (lognormal(0, 3), AoS): indices above
+    2^24 (beyond float precision), L = 25 in the fixed-point scale, and a
+    fallback prefix over 16.8 million weights; t_max 4096 and 0."""
+    rng = np.random.default_rng(21)
+    M, K = (1 << 24) + 7, 2
+    a = rng.lognormal(0, 3, size=(K, M)).astype(np.float32)
+    for t_max in (4096, 0):
+        g, o = dense_both(a, M, K, M, AOS, seed=5, step=t_max, t_max=t_max)
+        assert_same(g, o, f"M=2^24+7 t_max={t_max}")
+    assert np.all(g[0] >= 0)
+
+
 @pytest.mark.parametrize("t_max", [0, 1, 2, 3, 63, 127, 128, 129, 255, 4096])
 def test_trial_budgets_and_fallback(gpu, t_max):
     """Budgets that end inside a round, and forced fallbacks (t_max = 0)."""

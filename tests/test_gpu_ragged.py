@@ -88,6 +88,23 @@ def test_ragged_hard_chunks_and_fallbacks(gpu, restore_schedule, sched):
         assert np.any(g[2] == 4097)          # some rows still fell back
 
 
+def test_ragged_huge_instance(gpu):
+    """One instance of 2^24 + 7 reactions between two small ones: a hard row of
+    about a thousand chunks with host lists, and of 32 chunks of several LDS
+    pieces each with device-built lists; t_max 4096 and 0 (the fallback is
+    located from the chunk sums and searched in one chunk)."""
+    rng = np.random.default_rng(22)
+    sizes = np.array([5, (1 << 24) + 7, 100], np.int64)
+    offsets = np.zeros(4, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    alpha = rng.lognormal(0, 2, int(offsets[-1])).astype(np.float32)
+    for host in (True, False):
+        for t_max in (4096, 0):
+            g, o = _ragged_both(alpha, offsets, seed=3, step=t_max, t_max=t_max, host=host)
+            assert_same(g, o, f"huge instance host={host} t_max={t_max}")
+    assert g[0][1] >= 0
+
+
 def test_ragged_edge_instances(gpu):
     rng = np.random.default_rng(7)
     rows = [np.zeros(0), np.zeros(5), np.array([2.0]), rng.random(3000),

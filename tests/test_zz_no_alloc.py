@@ -84,6 +84,21 @@ def test_noalloc_hard_rows_in_pieces(gpu):
         arsel.set_schedule(s0)
 
 
+def test_noalloc_huge_instance(gpu):
+    """One instance of 2^24 + 7 reactions: 32 chunks of several LDS pieces each."""
+    rng = np.random.default_rng(23)
+    sizes = np.array([5, (1 << 24) + 7, 100], np.int64)
+    off = np.zeros(4, np.int64)
+    np.cumsum(sizes, out=off[1:])
+    alpha = rng.lognormal(0, 2, int(off[-1])).astype(np.float32)
+    rb = workloads.RaggedBatch(alpha=alpha, offsets=off, family=np.full(3, 2, np.int8))
+    for t_max in (4096, 0):
+        got, ref = _both(rb, seed=4, step=t_max, t_max=t_max)
+        _check(got, ref, f"t_max={t_max}")
+        o = oracle.select_ragged(alpha, off, seed=4, step=t_max, t_max=t_max, threads=8)
+        assert_same(got, o, f"t_max={t_max} vs oracle")
+
+
 def test_noalloc_rejects_oversized_batch(gpu):
     K = arsel.RAGGED_NOALLOC_MAX_K + 1
     a = torch.ones(K, dtype=torch.float32, device="cuda")
