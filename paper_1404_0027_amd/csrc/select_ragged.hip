@@ -578,7 +578,10 @@ __global__ __launch_bounds__(kHardThreads, 4) void k_ragged_hard(const float *al
             held = round;
 #pragma unroll
             for (int q = 0; q < kHardPer; ++q) {
-                const uint32_t b = round * (NT * kHardPer) + tid + NT * q;
+                uint32_t b = round * (NT * kHardPer) + tid + NT * q;
+                // the counter is chunk-invariant: keep the compiler from hoisting
+                // its Philox products out of the chunk loop (they spilled)
+                asm volatile("" : "+v"(b));
                 ja[q] = jb[q] = 0xFFFFFFFFu;
                 ua[q] = ub[q] = 0;
                 if (b < nblocks) {
