@@ -240,15 +240,16 @@ def select_ragged(alpha: torch.Tensor, offsets: torch.Tensor, *, seed: int, step
                   t_max: int = 4096, host_offsets=None, want_alpha0: bool = False,
                   want_trials: bool = False, index: torch.Tensor | None = None,
                   alpha0: torch.Tensor | None = None, trials: torch.Tensor | None = None):
-    """Uneven batch in one persistent launch (arsel_select_ragged).
+    """Uneven batch (arsel_select_ragged): scan, split, hard chunks, pick.
 
     alpha: float32 CUDA tensor of concatenated instances; offsets: int64 CUDA
     tensor [K+1].  host_offsets: the same offsets as a numpy array (optional);
-    when given, they are checked against alpha's size and the per-instance
-    sizes order the work longest first.  Repeated calls with the same sizes
-    (and schedule) reuse the work lists already on the device: the call is
-    then a single kernel launch.  Calls sharing a device context must run on
-    one stream, since the lists and counters live in the context.
+    when given, they are checked against alpha's size and the work lists are
+    built on the host (otherwise on the device, three more small launches).
+    Repeated calls with the same sizes (and schedule) reuse the work lists
+    already on the device: the call is then four kernel launches.  Calls
+    sharing a device context must run on one stream, since the lists and
+    counters live in the context.
     """
     import numpy as np
 

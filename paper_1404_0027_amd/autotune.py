@@ -1,8 +1,9 @@
 """Schedule autotuner for the selection kernels.
 
-The schedule of a launch -- wavefront vs workgroup per instance, waves per
-workgroup, which instances are staged in LDS, persistent workgroups per CU
-(ragged path); instances per tile and waves per workgroup (dense path) --
+The schedule of a launch -- the size up to which an instance is staged in one
+wavefront's LDS slice, waves per pick workgroup, the LDS piece (and chunk) of
+the hard rows, pick workgroups per CU (uneven batches); instances per tile and
+waves per workgroup (dense path) --
 never changes results (every schedule returns the sequential rule's answer),
 only speed.  The tuner times each candidate on the caller's own batch with
 HIP events and keeps the fastest; choices are cached per device and workload

@@ -29,10 +29,10 @@ extern "C" int arsel_create(arsel_ctx **out, int device)
     c->dense_tile = 16;
     c->dense_waves = 0;        // automatic (see launch_tile)
     c->trial_lanes = 0;
-    c->sched.wave_max_m = 1024;
+    c->sched.wave_max_m = 1024;   // the tuner's usual choice on log-uniform sizes
     c->sched.block_waves = 8;
-    c->sched.lds_max_m = 8192;
-    c->sched.blocks_per_cu = 2;
+    c->sched.lds_max_m = 0;       // hard piece 16380 floats
+    c->sched.blocks_per_cu = 4;
     c->queue = nullptr;
     c->order = nullptr;
     c->order_bytes = 0;

@@ -296,7 +296,7 @@ __device__ __forceinline__ uint32_t stream_bitmax(const float *src, uint32_t n, 
             dst[j] = x;
         });
     else
-        stream_each<NT>(src, n, tid, [&](uint32_t j, float x) { mb = max(mb, __float_as_uint(x)); });
+        stream_each<NT>(src, n, tid, [&](uint32_t, float x) { mb = max(mb, __float_as_uint(x)); });
     return mb;
 }
 
