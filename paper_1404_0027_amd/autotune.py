@@ -30,7 +30,7 @@ def ragged_candidates(lds_bytes: int) -> list[tuple[int, int, int, int]]:
     for wave_max_m in (256, 512, 1024, 2048, 4096):
         for block_waves in (4, 8, 16):
             for lds_max_m in (0, 4096, 8192):          # hard piece: 16380, 4096, 8192 floats
-                for bpc in (1, 2, 4):
+                for bpc in (1, 2, 4, 6, 8):
                     need = block_waves * wave_max_m * 4 + 2048
                     if need > lds_bytes or need * bpc > 160 * 1024:
                         continue
