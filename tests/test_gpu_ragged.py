@@ -110,7 +110,9 @@ def test_ragged_edge_instances(gpu):
     rows = [np.zeros(0), np.zeros(5), np.array([2.0]), rng.random(3000),
             np.r_[rng.random(100), np.nan], np.r_[rng.random(20000), -1.0],
             np.zeros(20000), np.full(70, 3e-44), rng.lognormal(0, 3, 40000),
-            np.r_[np.full(10, -0.0), 1.0], np.zeros(0), rng.random(64)]
+            np.r_[np.full(10, -0.0), 1.0], np.zeros(0), rng.random(64),
+            rng.random(5000) * 1e-40,                      # large, subnormal maximum
+            np.r_[rng.lognormal(0, 4, 30000) * 1e-45]]     # large, heavy-tailed subnormals
     sizes = np.array([len(r) for r in rows], np.int64)
     offsets = np.zeros(len(rows) + 1, np.int64)
     np.cumsum(sizes, out=offsets[1:])
