@@ -68,6 +68,10 @@ def lib() -> ctypes.CDLL:
         L.orc_ssa_run_proposal.argtypes = [P, i64, i64, i64, P, P, P, P, P, P, i64, u32, u32, P,
                                            u64, u64, i64, u32, P, P, P, i32]
         L.orc_ssa_run_proposal.restype = i32
+        L.orc_neg_ln_uniform.argtypes = [u32]
+        L.orc_neg_ln_uniform.restype = ctypes.c_double
+        L.orc_wide_alpha0.argtypes = [P, i64, i32]
+        L.orc_wide_alpha0.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -219,6 +223,24 @@ def ssa_run(net, X0: np.ndarray, *, seed: int, step0: int, steps: int, t_max: in
                                    qfloor, period, _p(idv), seed, step0, steps, t_max, _p(t),
                                    _p(times), _p(fired), threads)
     return x, t, fired, times
+
+
+def neg_ln_uniform(w: int) -> float:
+    """-ln u of the SSA time step for u = (w + 1/2) 2^-32 (Tang's table-driven ln)."""
+    return float(lib().orc_neg_ln_uniform(int(w) & 0xFFFFFFFF))
+
+
+def wide_alpha0(alpha, E: int) -> float:
+    """alpha_0 of the SSA time step: sum of floor(alpha_j 2^sh) over the finite
+    positive alpha_j, sh = 127 - ceil(log2 M) - E, rounded once to binary64 and
+    scaled back by 2^-sh."""
+    a = np.ascontiguousarray(alpha, dtype=np.float32).ravel()
+    return float(lib().orc_wide_alpha0(_p(a), a.shape[0], int(E)))
+
+
+def exponent_above(x: float) -> int:
+    """E with 2^(E-1) <= x < 2^E for a finite x > 0."""
+    return int(np.frexp(np.float32(x))[1])
 
 
 PAPER_REJECT = -5

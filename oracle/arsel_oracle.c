@@ -27,7 +27,9 @@
  *    it used (section "Materials").
  *  - Section "The Stochastic Simulation Algorithm" again for the SSA state
  *    update X <- X + v_j used by the jump-chain data generator, and for the
- *    direct method's time step tau = ln(1/u) / alpha_0 of the full SSA run.
+ *    direct method's time step tau = ln(1/u) / alpha_0 of the full SSA run,
+ *    with ln by Tang's published table-driven method and alpha_0 summed
+ *    exactly in 128-bit fixed point, then rounded once (both fixed below).
  *
  * Readings where the paper is silent are listed in the design notes; the
  * ones that fix arithmetic here: one Philox block b yields two trials,
@@ -464,13 +466,106 @@ int orc_ssa_chain(int32_t *X, int64_t R, int64_t N, int64_t M,
 }
 
 /* ------------------------------------------------------------------ */
+/* ln of the time step: P. T. P. Tang, "Table-driven implementation of   */
+/* the logarithm function in IEEE floating-point arithmetic", ACM TOMS   */
+/* 16(4), 1990, in this variant:                                        */
+/*   u = m 2^e with m in [0.75, 1.5);                                   */
+/*   c = i / 128, the breakpoint nearest m (ties to even), i in 96..192; */
+/*   r = (m - c) * fl(1 / c), where m - c is exact;                     */
+/*   log1p(r) by its Taylor polynomial of degree 7, r (1 - r/2 + ... +   */
+/*   r^6/7), the bracket by Horner's rule from 1/7 down with fused      */
+/*   multiply-adds, then one product with r;                            */
+/*   ln u = fma(e, fl(ln 2), fl(ln c)) + log1p(r).                      */
+/* fl(ln c) and fl(1 / c) are the rounded values (libm log of the exact  */
+/* i / 128, one IEEE division).  |r| <= 2^-8 / 0.75, so the first       */
+/* omitted term is below 2^-56 of log1p(r).                             */
+/* ------------------------------------------------------------------ */
+static double ln_c[193], inv_c[193];   /* entries 96..192 */
+static int ln_ready;
+
+static void ln_table_init(void)
+{
+    if (ln_ready) return;
+    for (int i = 96; i <= 192; ++i) {
+        ln_c[i] = log((double)i / 128.0);
+        inv_c[i] = 128.0 / (double)i;
+    }
+    ln_ready = 1;
+}
+
+/* -ln u for u = (w + 1/2) 2^-32, the time step's uniform. */
+static double neg_ln_uniform(uint32_t w)
+{
+    static const double coef[7] = {1.0 / 7.0, -1.0 / 6.0, 1.0 / 5.0, -1.0 / 4.0,
+                                   1.0 / 3.0, -1.0 / 2.0, 1.0};
+    const double u = ((double)w + 0.5) * 0x1p-32;
+    int e;
+    double m = frexp(u, &e);                  /* u = m 2^e, m in [0.5, 1) */
+    if (m < 0.75) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const int i = (int)nearbyint(m * 128.0);
+    const double r = (m - (double)i / 128.0) * inv_c[i];
+    double p = coef[0];
+    for (int k = 1; k < 7; ++k) p = fma(p, r, coef[k]);
+    return -(fma((double)e, M_LN2, ln_c[i]) + p * r);
+}
+
+double orc_neg_ln_uniform(uint32_t w)
+{
+    ln_table_init();
+    return neg_ln_uniform(w);
+}
+
+/* ------------------------------------------------------------------ */
+/* alpha_0 of the time step.  With a scale exponent E (2^(E-1) <= a      */
+/* maximum of the propensities < 2^E, chosen below) and                 */
+/* sh = 127 - L - E, each finite positive alpha_j contributes           */
+/* F_j = floor(alpha_j 2^sh) < 2^(127-L); S = sum F_j < 2^127 is exact   */
+/* in an unsigned 128-bit integer, and alpha_0 = fl64(S) 2^-sh (one     */
+/* rounding, to nearest even).  Every alpha_j >= 2^(E-103+L) is a whole */
+/* multiple of 2^-sh, so when the positive propensities lie within      */
+/* 104 - L binades of 2^E, alpha_0 is their exact sum rounded once;     */
+/* below that, the parts under 2^-sh are dropped (M 2^-sh at most).     */
+/* ------------------------------------------------------------------ */
+#define NO_SCALE (-100000)
+
+static int exponent_above(float a)
+{
+    int e;
+    (void)frexpf(a, &e);
+    return e;
+}
+
+static double wide_alpha0(const float *a, int64_t M, int E)
+{
+    const int sh = 127 - ceil_log2(M) - E;
+    unsigned __int128 S = 0;
+    for (int64_t j = 0; j < M; ++j)
+        if (a[j] > 0.0f && a[j] < INFINITY)
+            S += (unsigned __int128)floorl(ldexpl((long double)a[j], sh));
+    return ldexp((double)S, -sh);
+}
+
+double orc_wide_alpha0(const float *a, int64_t M, int E)
+{
+    return wide_alpha0(a, M, E);
+}
+
+/* ------------------------------------------------------------------ */
 /* Full SSA run (direct method, section "The Stochastic Simulation      */
 /* Algorithm"): each step recomputes every propensity from the state,   */
 /* selects the next reaction, advances the time by                      */
 /* tau = ln(1/u) / alpha_0 and applies the stoichiometry.  u comes from */
 /* Philox block 0xFFFFFFFE of the tag-2 stream (instance id, step s),    */
-/* word 0, as (w + 1/2) 2^-32 in (0, 1); alpha_0 is the binary64 sum of  */
-/* the propensities in index order.  An invalid propensity records -2   */
+/* word 0, as (w + 1/2) 2^-32 in (0, 1); -ln u is neg_ln_uniform and    */
+/* alpha_0 is wide_alpha0 with the scale exponent E: at the call's first */
+/* step and at steps with s mod p = 0 (the exact steps, below), E is    */
+/* that of alpha_max (none when a propensity is invalid or all are      */
+/* zero); between them E stays while every valid propensity is below    */
+/* 2^E and is dropped once one reaches it; a step that fires with no E  */
+/* takes that of its own alpha_max.  An invalid propensity records -2   */
 /* and every propensity zero records -1; state and time then stay.      */
 /*                                                                      */
 /* Selection: uniform AR on the tag-2 stream (the jump chain's) with    */
@@ -496,6 +591,7 @@ static int ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M, const int32_t *r
                    uint32_t t_max, double *t, double *times, int32_t *fired, int threads)
 {
     if (period == 0) period = 1;
+    ln_table_init();
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #pragma omp parallel if (threads != 1)
@@ -519,17 +615,23 @@ static int ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M, const int32_t *r
             }
             float B = 0.0f;
             double C = 0.0;
+            int E = NO_SCALE;
             for (int64_t i = 0; i < steps; ++i) {
                 const uint64_t s = step0 + (uint64_t)i;
                 const int exact = i == 0 || s % period == 0;
-                double a0 = 0.0;
+                float vmax = 0.0f;             /* largest valid propensity */
                 for (int64_t j = 0; j < M; ++j) {
                     a[j] = mass_action(x, r0[j], r1[j], rate[j]);
-                    a0 += (double)a[j];
+                    if (a[j] >= 0.0f && a[j] < INFINITY && a[j] > vmax) vmax = a[j];
                 }
                 float amax;
+                const int ok = scan_max(a, 1, M, &amax) == 0;
+                if (exact)
+                    E = ok && amax > 0.0f ? exponent_above(amax) : NO_SCALE;
+                else if (E != NO_SCALE && (double)vmax >= ldexp(1.0, E))
+                    E = NO_SCALE;
                 int32_t j;
-                if (scan_max(a, 1, M, &amax) != 0) {
+                if (!ok) {
                     j = -2;
                 } else if (amax == 0.0f) {
                     j = -1;
@@ -550,8 +652,8 @@ static int ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M, const int32_t *r
                 if (j >= 0) {
                     uint32_t w[4];
                     draw(seed, TAU_BLOCK, id, s, 2u, w);
-                    const double u = ((double)w[0] + 0.5) * 0x1p-32;
-                    t[r] += log(1.0 / u) / a0;
+                    if (E == NO_SCALE) E = exponent_above(amax);
+                    t[r] += neg_ln_uniform(w[0]) / wide_alpha0(a, M, E);
                     x[r0[j]] -= 1;
                     if (r1[j] >= 0) x[r1[j]] -= 1;
                     x[p0[j]] += 1;
