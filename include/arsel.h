@@ -281,10 +281,21 @@ int arsel_ssa_deps(arsel_ctx *ctx, const arsel_network *net, int32_t *deps, int3
  * 0xFFFFFFFE of the same stream, applies the stoichiometry and recomputes the
  * propensities of the reactions deps lists for j.
  *
+ * The time step's arithmetic is fixed: -ln u by Tang's table-driven method
+ * (breakpoints i/128, m in [0.75, 1.5), log1p by its degree-7 series with
+ * fused multiply-adds); alpha_0 = fl64(S) 2^-sh with S the sum of
+ * floor(alpha_j 2^sh) over the finite positive alpha_j in 128-bit integers,
+ * sh = 127 - ceil(log2 M) - E and 2^(E-1) <= alpha_max < 2^E at the scale's
+ * last setting: steps with exact envelopes set E, a propensity reaching 2^E
+ * drops it, and a step that fires with no E or with S < 2^(95 - ceil(log2 M))
+ * takes E from its own alpha_max.  alpha_0 is then the exact sum rounded once
+ * to binary64 when the positive propensities lie within 104 - ceil(log2 M)
+ * binades of 2^E, and within 2^(2 ceil(log2 M) - 95) of it otherwise.
+ *
  * Bound maintenance: the envelope B of the acceptance test (and alpha_0) is
  * exact at the call's first step and at steps with s mod period = 0; between
  * them B is the running maximum of alpha_max since then, kept from the
- * changed propensities, and alpha_0 is updated by their differences.  Any
+ * changed propensities, and S is updated by their differences.  Any
  * B >= alpha_max leaves the law alpha_j / alpha_0 of every step; the
  * fallback uses the exact alpha_max.  period 0 or 1: exact at every step (one
  * pass over the M propensities per step); a larger period makes a step read
@@ -298,10 +309,8 @@ int arsel_ssa_deps(arsel_ctx *ctx, const arsel_network *net, int32_t *deps, int3
  *
  * An invalid propensity (NaN, negative, +inf) records -2 and no positive one
  * -1; the state and time then stay.  fired (nullable, [steps][R]) and times
- * (nullable, [steps][R], t after each step) are outputs.  States and
- * selections are bit-identical to the sequential definition; the times agree
- * with it to rounding (the sum order of alpha_0, its updates between exact
- * steps and the log implementation differ). */
+ * (nullable, [steps][R], t after each step) are outputs.  States,
+ * selections and times are bit-identical to the sequential definition. */
 int arsel_ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps,
                   const int32_t *ndeps, int32_t *X, int32_t R, uint64_t seed, uint64_t step0,
                   int64_t steps, uint32_t t_max, uint32_t period, double *t, double *times,

@@ -528,6 +528,8 @@ double orc_neg_ln_uniform(uint32_t w)
 /* multiple of 2^-sh, so when the positive propensities lie within      */
 /* 104 - L binades of 2^E, alpha_0 is their exact sum rounded once;     */
 /* below that, the parts under 2^-sh are dropped (M 2^-sh at most).     */
+/* The run keeps S >= 2^(95-L) (alpha_0 >= 2^(E-32)), so the dropped     */
+/* parts stay below 2^(2L-95) of alpha_0.                               */
 /* ------------------------------------------------------------------ */
 #define NO_SCALE (-100000)
 
@@ -538,14 +540,31 @@ static int exponent_above(float a)
     return e;
 }
 
-static double wide_alpha0(const float *a, int64_t M, int E)
+/* floor(a 2^sh) for finite a > 0: a = f 2^e with f in [0.5, 1), so
+ * a = n 2^(e-24) with the integer n = f 2^24 < 2^24, and the floor is n
+ * shifted by e - 24 + sh (right shifts drop the fraction). */
+static unsigned __int128 wide_weight(float a, int sh)
+{
+    int e;
+    const float f = frexpf(a, &e);
+    const unsigned __int128 n = (uint32_t)ldexpf(f, 24);
+    const int s = e - 24 + sh;
+    if (s >= 0) return n << s;
+    return s > -32 ? n >> -s : 0;
+}
+
+static unsigned __int128 wide_sum(const float *a, int64_t M, int E)
 {
     const int sh = 127 - ceil_log2(M) - E;
     unsigned __int128 S = 0;
     for (int64_t j = 0; j < M; ++j)
-        if (a[j] > 0.0f && a[j] < INFINITY)
-            S += (unsigned __int128)floorl(ldexpl((long double)a[j], sh));
-    return ldexp((double)S, -sh);
+        if (a[j] > 0.0f && a[j] < INFINITY) S += wide_weight(a[j], sh);
+    return S;
+}
+
+static double wide_alpha0(const float *a, int64_t M, int E)
+{
+    return ldexp((double)wide_sum(a, M, E), -(127 - ceil_log2(M) - E));
 }
 
 double orc_wide_alpha0(const float *a, int64_t M, int E)
@@ -564,8 +583,9 @@ double orc_wide_alpha0(const float *a, int64_t M, int E)
 /* step and at steps with s mod p = 0 (the exact steps, below), E is    */
 /* that of alpha_max (none when a propensity is invalid or all are      */
 /* zero); between them E stays while every valid propensity is below    */
-/* 2^E and is dropped once one reaches it; a step that fires with no E  */
-/* takes that of its own alpha_max.  An invalid propensity records -2   */
+/* 2^E and is dropped once one reaches it; a step that fires with no E, */
+/* or with S < 2^(95-L) at E (alpha_0 fell 32 binades below 2^E), takes */
+/* E from its own alpha_max.  An invalid propensity records -2          */
 /* and every propensity zero records -1; state and time then stay.      */
 /*                                                                      */
 /* Selection: uniform AR on the tag-2 stream (the jump chain's) with    */
@@ -652,8 +672,15 @@ static int ssa_run(int32_t *X, int64_t R, int64_t N, int64_t M, const int32_t *r
                 if (j >= 0) {
                     uint32_t w[4];
                     draw(seed, TAU_BLOCK, id, s, 2u, w);
-                    if (E == NO_SCALE) E = exponent_above(amax);
-                    t[r] += neg_ln_uniform(w[0]) / wide_alpha0(a, M, E);
+                    const int L = ceil_log2(M);
+                    unsigned __int128 S = 0;
+                    if (E != NO_SCALE) S = wide_sum(a, M, E);
+                    if (E != NO_SCALE && S < (unsigned __int128)1 << (95 - L)) E = NO_SCALE;
+                    if (E == NO_SCALE) {
+                        E = exponent_above(amax);
+                        S = wide_sum(a, M, E);
+                    }
+                    t[r] += neg_ln_uniform(w[0]) / ldexp((double)S, -(127 - L - E));
                     x[r0[j]] -= 1;
                     if (r1[j] >= 0) x[r1[j]] -= 1;
                     x[p0[j]] += 1;

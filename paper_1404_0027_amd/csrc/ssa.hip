@@ -164,6 +164,153 @@ __device__ __forceinline__ double neg_ln_u(uint32_t w, const double *tab)
     return -((fma((double)e, 0.69314718055994530942, lnc)) + l1p);
 }
 
+// ---- alpha_0 of the time step in 128-bit fixed point ----
+//
+// With a scale exponent E (2^(E-1) <= a maximum of the propensities < 2^E)
+// and sh = 127 - L - E, L = ceil(log2 M), the propensity with bits b weighs
+// F(b) = floor(v 2^sh) < 2^(127-L) when v is finite and positive, 0
+// otherwise; S = sum_j F(b_j) < 2^127 is exact, and alpha_0 = fl64(S) 2^-sh
+// is rounded once.  Every v >= 2^(E-103+L) is a whole multiple of 2^-sh, so
+// when the positive propensities lie within 104 - L binades of 2^E alpha_0
+// is their exact sum rounded once, whatever their order.  The run keeps S
+// from the changed propensities' differences (mod 2^128) and rebuilds it
+// when E changes.  E is set at the steps with exact envelopes to that of
+// alpha_max, stays while every valid propensity is below 2^E, and is
+// dropped when one reaches it; a step that fires with no E, or with
+// S < 2^(95-L) (alpha_0 fell 32 binades below 2^E), takes E from its own
+// alpha_max, so the dropped parts stay below 2^(2L-95) of alpha_0.
+struct U128 {
+    uint64_t lo, hi;
+};
+
+__device__ __forceinline__ U128 add128(U128 a, U128 b)
+{
+    U128 r;
+    r.lo = a.lo + b.lo;
+    r.hi = a.hi + b.hi + (uint64_t)(r.lo < a.lo);
+    return r;
+}
+
+__device__ __forceinline__ U128 sub128(U128 a, U128 b)
+{
+    U128 r;
+    r.lo = a.lo - b.lo;
+    r.hi = a.hi - b.hi - (uint64_t)(a.lo < b.lo);
+    return r;
+}
+
+constexpr int kNoScale = -100000;
+
+// F(b) at the shift sh: v = m 2^(max(e,1) - 150) with m the 24-bit
+// significand, so F = m 2^k with k = max(e,1) - 150 + sh, k <= 103 for
+// v < 2^E.  The low word is m << k (k in 0..63) or m >> -k (k < 0); the high
+// word holds m >> (64 - k) for k in 41..63 and m << (k - 64) for k >= 64.
+// Shift amounts are masked to 0..63; values at or above 2^E (which drop the
+// scale) give some value that is never used.
+__device__ __forceinline__ U128 wide_weight(uint32_t b, int sh)
+{
+    const uint32_t e = b >> 23;
+    const uint64_t m = b < 0x7F800000u ? (uint64_t)((b & 0x7FFFFFu) | (e ? 0x800000u : 0u)) : 0ull;
+    const int k = (int)max(e, 1u) - 150 + sh;
+    const uint64_t up = m << (k & 63);
+    const uint64_t dn = m >> (min(-k, 63) & 63);
+    const uint64_t sp = m >> ((64 - k) & 63);
+    U128 r;
+    r.lo = k >= 64 ? 0ull : (k >= 0 ? up : dn);
+    r.hi = k >= 64 ? up : (k > 40 ? sp : 0ull);
+    return r;
+}
+
+// F(nv) - F(old) mod 2^128, invalid values counting as 0.  When the
+// smaller nonzero exponent puts both on the grid (k >= 0) and the two lie
+// within 38 binades, their significands aligned to that exponent differ by
+// an exact int64 delta and the difference is delta 2^k; otherwise the two
+// weights are taken apart.
+__device__ __forceinline__ U128 wide_delta(float old, float nv, int sh)
+{
+    const uint32_t bo = __float_as_uint(old), bn = __float_as_uint(nv);
+    const uint32_t co = bo < 0x7F800000u ? bo : 0u, cn = bn < 0x7F800000u ? bn : 0u;
+    const uint32_t eo = co >> 23, en = cn >> 23;
+    const uint64_t mo = (co & 0x7FFFFFu) | (eo ? 0x800000u : 0u);
+    const uint64_t mn = (cn & 0x7FFFFFu) | (en ? 0x800000u : 0u);
+    const int xo = (int)max(eo, 1u), xn = (int)max(en, 1u);
+    const int xb = min(co ? xo : 255, cn ? xn : 255);   // 255: both zero, delta 0
+    const int go = xo - xb, gn = xn - xb;         // a zero value may give < 0: its m is 0
+    const int k = xb - 150 + sh;
+    U128 r;
+    if (k >= 0 && max(go, gn) <= 38) {
+        const int64_t dl = (int64_t)(mn << (gn & 63)) - (int64_t)(mo << (go & 63));
+        const uint64_t sl = (uint64_t)dl << (k & 63);
+        const uint64_t sr = (uint64_t)(dl >> ((64 - k) & 63));
+        r.lo = k < 64 ? sl : 0ull;
+        r.hi = k >= 64 ? sl : (k == 0 ? (uint64_t)(dl >> 63) : sr);
+    } else {
+        r = sub128(wide_weight(cn, sh), wide_weight(co, sh));
+    }
+    return r;
+}
+
+// Bits of the float 2^E (E in -148..128; 2^128 gives the bits of +inf, which
+// no finite value reaches).
+__device__ __forceinline__ uint32_t pow2_bits(int E)
+{
+    return E >= -126 ? (uint32_t)(E + 127) << 23 : 1u << (E + 149);
+}
+
+// fl64(S) 2^-sh, rounded to nearest even once: for S >= 2^64 the top 64
+// bits are converted with the bits below them folded into the last bit
+// (they lie below the rounding position), then scaled back.  S < 2^127.
+__device__ __forceinline__ double wide_to_f64(U128 s, int sh)
+{
+    const int n = s.hi ? 64 - __clzll((long long)s.hi) : 0;     // 0..63
+    const uint64_t top = n ? (s.hi << ((64 - n) & 63)) | (s.lo >> n) |
+                                 (uint64_t)((s.lo << ((64 - n) & 63)) != 0)
+                           : s.lo;
+    return ldexp((double)top, n - sh);
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ U128 dpp_add128(U128 x)
+{
+    U128 y;
+    y.lo = dpp_u64<CTRL, ROW_MASK>(x.lo);
+    y.hi = dpp_u64<CTRL, ROW_MASK>(x.hi);
+    return add128(x, y);
+}
+
+__device__ __forceinline__ U128 readlane128(U128 x, int l)
+{
+    U128 r;
+    r.lo = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x.lo, l) |
+           ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x.lo >> 32), l) << 32);
+    r.hi = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x.hi, l) |
+           ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x.hi >> 32), l) << 32);
+    return r;
+}
+
+// Sums mod 2^128 over the wavefront, over lanes 0..15, and over each 32-lane
+// half (the DPP patterns of the binary64 sums); every lane returns its sum.
+__device__ __forceinline__ U128 wave_sum_u128(U128 x)
+{
+    x = dpp_add128<0x111>(x);
+    x = dpp_add128<0x112>(x);
+    x = dpp_add128<0x114>(x);
+    x = dpp_add128<0x118>(x);
+    x = dpp_add128<0x142, 0xA>(x);
+    x = dpp_add128<0x143, 0xC>(x);
+    return readlane128(x, 63);
+}
+
+// Sum of lanes 0..15 (row 0); every lane returns it.
+__device__ __forceinline__ U128 row0_sum_u128(U128 x)
+{
+    x = dpp_add128<0x111>(x);
+    x = dpp_add128<0x112>(x);
+    x = dpp_add128<0x114>(x);
+    x = dpp_add128<0x118>(x);
+    return readlane128(x, 15);
+}
+
 struct RunArgs {
     NetArgs net;
     const int32_t *deps, *ndeps;
@@ -266,11 +413,12 @@ __device__ __forceinline__ void wave_sum_pair(int32_t &a, int32_t &b)
 //
 // Bound maintenance with period p: at the call's first step and at steps
 // s with s mod p = 0 one pass over the propensities takes the exact
-// alpha_max (the envelope B), alpha_0, the numbers of positive and of invalid
+// alpha_max (the envelope B), the numbers of positive and of invalid
 // propensities and, with a proposal, the exact c; between those steps the
-// update of the affected reactions keeps the counts, alpha_0 (incrementally,
-// to rounding) and the running maxima B and C, so a step reads only its
-// candidates and the changed reactions.  B >= alpha_max and C >= max_j
+// update of the affected reactions keeps the counts and the running maxima
+// B and C, so a step reads only its candidates and the changed reactions.
+// alpha_0 of the time step is the 128-bit fixed-point sum S (above), kept
+// from the changed reactions' differences at every period.  B >= alpha_max and C >= max_j
 // alpha_j / Q'_j keep each step's law alpha_j / alpha_0; the fallback still
 // uses the exact alpha_max.  p = 1 takes the pass at every step.
 //
@@ -280,7 +428,7 @@ __device__ __forceinline__ void wave_sum_pair(int32_t &a, int32_t &b)
 // on the tag-1 stream.  An invalid propensity gives -2 and no positive one
 // -1 (both permanent: nothing fires), sum Q' >= 2^32 gives -4.
 template <int NW, bool PROP>
-__global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
+__global__ __launch_bounds__(NW * 64, PROP ? 1 : 5) void k_ssa_run(RunArgs c)
 {
     static_assert(kDepMax == kWave, "one dependency row per wavefront load");
     extern __shared__ int32_t lds_i[];
@@ -311,9 +459,12 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
     wave_sync_lds();
     auto qat = [&](uint32_t jj) { return sp[jj] - (jj ? sp[jj - 1] : 0u); };
     const uint64_t period = max(c.period, 1u);
-    const bool maintain = period > 1;   // with period 1 nothing is kept across steps
+    const bool maintain = period > 1;   // with period 1 the envelopes are not kept across steps
+    const int L = ceil_log2_u32((uint32_t)M);
     double t = c.t[r];
-    double a0 = 0.0;     // alpha_0 (exact at refresh steps, updated between)
+    U128 S{0, 0};        // sum of F at the scale Es (when have)
+    int Es = kNoScale;
+    bool have = false;
     float B = 0.0f;      // envelope >= alpha_max (uniform)
     double C = 0.0;      // envelope >= max_j alpha_j / Q'_j (proposal)
     int32_t npos = 0, nbad = 0;
@@ -323,14 +474,12 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
         if (exact) {
             uint32_t mb = 0;
             float rmax = 0.0f;
-            a0 = 0.0;
             if (maintain) {
                 npos = 0;
                 nbad = 0;
                 for (int j = lane; j < M; j += kWave) {
                     const float v = a[j];
                     mb = max(mb, __float_as_uint(v) & 0x7FFFFFFFu);   // alpha_max while all are valid
-                    a0 += (double)v;
                     npos += v > 0.0f;
                     nbad += !valid_prop(v);
                     if (PROP && v > 0.0f) rmax = fmaxf(rmax, ratio_estimate(v, qat((uint32_t)j)));
@@ -343,7 +492,6 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
                 for (int j = lane; j < M; j += kWave) {
                     const float v = a[j];
                     mb = max(mb, __float_as_uint(v));
-                    a0 += (double)v;
                     if (PROP && v > 0.0f) rmax = fmaxf(rmax, ratio_estimate(v, qat((uint32_t)j)));
                 }
                 mb = wave_max_u32(mb);
@@ -355,7 +503,16 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
                 nbad = bad ? 1 : 0;
                 npos = B > 0.0f ? 1 : 0;
             }
-            a0 = wave_sum_f64_dpp(a0);
+            if (nbad == 0 && npos > 0) {
+                const int e = exponent_above(B);      // B is alpha_max here
+                if (e != Es) {
+                    Es = e;
+                    have = false;
+                }
+            } else {
+                Es = kNoScale;
+                have = false;
+            }
             if (PROP && nbad == 0 && npos > 0 && sumq < (1ull << 32))
                 C = wave_proposal_c_band(a, (uint32_t)M, qat, wave_max_f32_nonneg(rmax));
         }
@@ -388,7 +545,26 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
             const int32_t nd = c.ndeps[j];
             const int4 dl = c.tab[(int64_t)j * kDepMax + lane];
             const int32_t jr0 = c.net.r0[j], jr1 = c.net.r1[j], jp0 = c.net.p0[j], jp1 = c.net.p1[j];
-            t += neg_ln_u(uniform_u32(tau_w), c.ln_tab) / a0;
+            if (have && S.hi < (1ull << (31 - L))) {       // alpha_0 < 2^(Es-32)
+                Es = kNoScale;
+                have = false;
+            }
+            if (!have) {
+                if (Es == kNoScale) {
+                    uint32_t mb = 0;
+                    for (int jj = lane; jj < M; jj += kWave)
+                        mb = max(mb, __float_as_uint(a[jj]) & 0x7FFFFFFFu);
+                    Es = exponent_above(__uint_as_float(wave_max_u32(mb)));
+                }
+                const int sh = 127 - L - Es;
+                U128 acc{0, 0};
+                for (int jj = lane; jj < M; jj += kWave)
+                    acc = add128(acc, wide_weight(__float_as_uint(a[jj]), sh));
+                S = wave_sum_u128(acc);
+                have = true;
+            }
+            const int sh = 127 - L - Es;
+            t += neg_ln_u(uniform_u32(tau_w), c.ln_tab) / wide_to_f64(S, sh);
             if (lane == 0) {
                 x[jr0] -= 1;
                 if (jr1 >= 0) x[jr1] -= 1;
@@ -396,11 +572,19 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
                 if (jp1 >= 0) x[jp1] += 1;
             }
             wave_sync_lds();
+            // S from the changed reactions' differences; a valid new value at
+            // or above 2^Es drops the scale
+            const uint32_t sthr = pow2_bits(Es);
+            U128 d{0, 0};
+            bool up = false;
+            auto track = [&](float old, float nv) {
+                d = add128(d, wide_delta(old, nv, sh));
+                up |= __float_as_uint(nv) < 0x7F800000u && __float_as_uint(nv) >= sthr;
+            };
             if (maintain) {
-                // count changes from ballots (wave-uniform), alpha_0 from the
-                // lanes' differences, the envelope only when a new value
-                // exceeds it
-                double da0 = 0.0, cm = 0.0;
+                // count changes from ballots (wave-uniform), the envelope only
+                // when a new value exceeds it
+                double cm = 0.0;
                 uint32_t bm = 0;
                 auto update = [&](bool on, int jj, int32_t ra, int32_t rb, float k) {
                     float old = 0.0f, nv = 0.0f;
@@ -408,7 +592,7 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
                         old = a[jj];
                         nv = mass_action(x, ra, rb, k);
                         a[jj] = nv;
-                        da0 += (double)nv - (double)old;
+                        track(old, nv);
                         if (valid_prop(nv)) {
                             if (!PROP) bm = max(bm, __float_as_uint(nv) & 0x7FFFFFFFu);
                             if (PROP && nv > 0.0f)
@@ -429,19 +613,28 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run(RunArgs c)
                 } else {
                     update(lane < nd, dl.x, dl.y, dl.z, __int_as_float(dl.w));
                 }
-                a0 += (nd >= 0 && nd <= 16) ? row0_sum_f64(da0) : wave_sum_f64_dpp(da0);
                 if (PROP) {
                     if (__ballot(cm > C)) C = fmax(C, wave_max_f64_nonneg(cm));
                 } else {
                     if (__ballot(bm > __float_as_uint(B))) B = fmaxf(B, __uint_as_float(wave_max_u32(bm)));
                 }
             } else {
+                auto update = [&](int jj, int32_t ra, int32_t rb, float k) {
+                    const float old = a[jj], nv = mass_action(x, ra, rb, k);
+                    a[jj] = nv;
+                    track(old, nv);
+                };
                 if (nd < 0) {
                     for (int jj = lane; jj < M; jj += kWave)
-                        a[jj] = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+                        update(jj, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
                 } else if (lane < nd) {
-                    a[dl.x] = mass_action(x, dl.y, dl.z, __int_as_float(dl.w));
+                    update(dl.x, dl.y, dl.z, __int_as_float(dl.w));
                 }
+            }
+            S = add128(S, (nd >= 0 && nd <= 16) ? row0_sum_u128(d) : wave_sum_u128(d));
+            if (__ballot(up)) {
+                Es = kNoScale;
+                have = false;
             }
             wave_sync_lds();
         }
@@ -491,21 +684,15 @@ __device__ __forceinline__ uint32_t half_max_u32(uint32_t x)
                      (uint32_t)__builtin_amdgcn_readlane((int)x, 63));
 }
 
-__device__ __forceinline__ double half_sum_f64(double x)
+__device__ __forceinline__ U128 half_sum_u128(U128 x)
 {
-    auto bits = [](double v) { return (uint64_t)__double_as_longlong(v); };
-    auto dbl = [](uint64_t b) { return __longlong_as_double((long long)b); };
-    x += dbl(dpp_u64<0x111>(bits(x)));
-    x += dbl(dpp_u64<0x112>(bits(x)));
-    x += dbl(dpp_u64<0x114>(bits(x)));
-    x += dbl(dpp_u64<0x118>(bits(x)));
-    x += dbl(dpp_u64<0x142, 0xA>(bits(x)));
-    const uint64_t b = bits(x);
-    const uint32_t lo = half_pick((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 31),
-                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63));
-    const uint32_t hi = half_pick((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 31),
-                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63));
-    return dbl((uint64_t)lo | ((uint64_t)hi << 32));
+    x = dpp_add128<0x111>(x);
+    x = dpp_add128<0x112>(x);
+    x = dpp_add128<0x114>(x);
+    x = dpp_add128<0x118>(x);
+    x = dpp_add128<0x142, 0xA>(x);
+    const U128 s0 = readlane128(x, 31), s1 = readlane128(x, 63);
+    return (lane_id() & 32) ? s1 : s0;
 }
 
 // 64-bit shuffles within the 32-lane half (the fallback's rare path).
@@ -583,8 +770,11 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
     wave_sync_lds();
     const uint64_t period = max(c.period, 1u);
     const bool maintain = period > 1;
+    const int L = ceil_log2_u32((uint32_t)M);
     double t = live ? c.t[r] : 0.0;
-    double a0 = 0.0;
+    U128 S{0, 0};        // each half's alpha_0 sum (k_ssa_run)
+    int Es = kNoScale;
+    bool have = false;
     float B = 0.0f;
     int32_t npos = 0, nbad = 0;
     const uint32_t thresh = lemire_threshold((uint32_t)M);
@@ -593,18 +783,25 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
         const bool exact = i == 0 || s % period == 0;
         if (exact) {
             uint32_t mb = 0, cnt = 0;
-            double ap = 0.0;
             for (int j = hl; j < M; j += 32) {
                 const float v = a[j];
                 mb = max(mb, __float_as_uint(v) & 0x7FFFFFFFu);
-                ap += (double)v;
                 cnt += (uint32_t)(v > 0.0f) + ((uint32_t)!valid_prop(v) << 16);
             }
             B = __uint_as_float(half_max_u32(mb));
-            a0 = half_sum_f64(ap);
             cnt = half_sum_u32(cnt);
             npos = live ? (int32_t)(cnt & 0xFFFFu) : 0;
             nbad = live ? (int32_t)(cnt >> 16) : 0;
+            if (nbad == 0 && npos > 0) {
+                const int e = exponent_above(B);
+                if (e != Es) {
+                    Es = e;
+                    have = false;
+                }
+            } else {
+                Es = kNoScale;
+                have = false;
+            }
         }
         // the step's selection: -2 / -1 decided, else the rounds
         int32_t j = nbad ? -2 : -1;
@@ -657,7 +854,31 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
             const int4 d0 = c.tab[(int64_t)jf * kDepMax + hl];
             const int4 d1 = c.tab[(int64_t)jf * kDepMax + 32 + hl];
             const int32_t jr0 = c.net.r0[jf], jr1 = c.net.r1[jf], jp0 = c.net.p0[jf], jp1 = c.net.p1[jf];
-            if (fire) t += neg_ln_u(tau_w, c.ln_tab) / a0;
+            if (fire && have && S.hi < (1ull << (31 - L))) {   // alpha_0 < 2^(Es-32)
+                Es = kNoScale;
+                have = false;
+            }
+            const bool need = fire && !have;
+            if (__ballot(need)) {
+                const bool scan = need && Es == kNoScale;
+                if (__ballot(scan)) {
+                    uint32_t mb = 0;
+                    for (int jj = hl; jj < M; jj += 32) mb = max(mb, __float_as_uint(a[jj]) & 0x7FFFFFFFu);
+                    mb = half_max_u32(mb);
+                    if (scan) Es = exponent_above(__uint_as_float(mb));
+                }
+                const int shn = 127 - L - Es;
+                U128 acc{0, 0};
+                for (int jj = hl; jj < M; jj += 32)
+                    acc = add128(acc, wide_weight(__float_as_uint(a[jj]), shn));
+                acc = half_sum_u128(acc);
+                if (need) {
+                    S = acc;
+                    have = true;
+                }
+            }
+            const int sh = 127 - L - Es;
+            if (fire) t += neg_ln_u(tau_w, c.ln_tab) / wide_to_f64(S, sh);
             if (fire && hl == 0) {
                 x[jr0] -= 1;
                 if (jr1 >= 0) x[jr1] -= 1;
@@ -666,15 +887,21 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
             }
             wave_sync_lds();
             const bool full = fire && nd < 0;
+            const uint32_t sthr = fire ? pow2_bits(Es) : 0xFFFFFFFFu;
+            U128 d{0, 0};
+            bool up = false;
+            auto track = [&](float old, float nv) {
+                d = add128(d, wide_delta(old, nv, sh));
+                up |= __float_as_uint(nv) < 0x7F800000u && __float_as_uint(nv) >= sthr;
+            };
             if (maintain) {
-                double da0 = 0.0;
                 uint32_t bm = 0;
                 int32_t dpos = 0, dbad = 0;
                 auto update = [&](int jj, int32_t ra, int32_t rb, float k) {
                     const float old = a[jj];
                     const float nv = mass_action(x, ra, rb, k);
                     a[jj] = nv;
-                    da0 += (double)nv - (double)old;
+                    track(old, nv);
                     if (valid_prop(nv)) bm = max(bm, __float_as_uint(nv) & 0x7FFFFFFFu);
                     dpos += (int32_t)(nv > 0.0f) - (int32_t)(old > 0.0f);
                     dbad += (int32_t)!valid_prop(nv) - (int32_t)!valid_prop(old);
@@ -690,16 +917,37 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
                 const int32_t sp = (int32_t)(int16_t)(tot & 0xFFFF);
                 npos += sp;
                 nbad += (tot - sp) / 65536;
-                a0 += half_sum_f64(da0);
                 if (__ballot(bm > __float_as_uint(B))) B = fmaxf(B, __uint_as_float(half_max_u32(bm)));
             } else {
+                auto update = [&](int jj, int32_t ra, int32_t rb, float k) {
+                    const float old = a[jj], nv = mass_action(x, ra, rb, k);
+                    a[jj] = nv;
+                    track(old, nv);
+                };
                 if (full) {
                     for (int jj = hl; jj < M; jj += 32)
-                        a[jj] = mass_action(x, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
+                        update(jj, c.net.r0[jj], c.net.r1[jj], c.net.rate[jj]);
                 } else if (fire) {
-                    if (hl < nd) a[d0.x] = mass_action(x, d0.y, d0.z, __int_as_float(d0.w));
-                    if (32 + hl < nd) a[d1.x] = mass_action(x, d1.y, d1.z, __int_as_float(d1.w));
+                    if (hl < nd) update(d0.x, d0.y, d0.z, __int_as_float(d0.w));
+                    if (32 + hl < nd) update(d1.x, d1.y, d1.z, __int_as_float(d1.w));
                 }
+            }
+            // with at most 16 changes per half they sit in rows 0 and 2
+            const int nmax = max(__builtin_amdgcn_readlane(nd, 0), __builtin_amdgcn_readlane(nd, 32));
+            if (__ballot(full) || nmax > 16) {
+                d = half_sum_u128(d);
+            } else {
+                d = dpp_add128<0x111>(d);
+                d = dpp_add128<0x112>(d);
+                d = dpp_add128<0x114>(d);
+                d = dpp_add128<0x118>(d);
+                const U128 s0 = readlane128(d, 15), s1 = readlane128(d, 47);
+                d = (lane & 32) ? s1 : s0;
+            }
+            if (fire) S = add128(S, d);
+            if ((uint32_t)(__ballot(up) >> (lane & 32))) {
+                Es = kNoScale;
+                have = false;
             }
             wave_sync_lds();
         }

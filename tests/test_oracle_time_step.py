@@ -163,3 +163,43 @@ def test_run_times_step_by_step(period, spread):
                 assert times[i, r] == prev
             prev = times[i, r]
         assert t[r] == prev
+
+
+def _collapse_net():
+    # species A, B, C; A -> C at rate 2^60 fires first (with probability
+    # 1 - 1e-31), then B -> C and C -> B run with propensities near 2^-47
+    i32 = lambda v: np.array(v, np.int32)
+    return workloads.Network(N=3, r0=i32([0, 1, 2]), r1=i32([-1, -1, -1]), p0=i32([2, 2, 1]),
+                             p1=i32([-1, -1, -1]),
+                             rate=np.array([2.0 ** 60, 1.2345e-15, 1.3e-15], np.float32))
+
+
+@pytest.mark.parametrize("period", [1, 64])
+def test_scale_is_taken_again_after_a_collapse(period):
+    """After the 2^60 propensity collapses, the sum at the old scale (E = 61,
+    sh = 64) keeps only about 17 bits of the propensities near 2^-47; it is
+    below 2^(95-L), so the next step that fires takes the scale from its own
+    alpha_max and alpha_0 is again the exact sum rounded once.  Without that
+    rule most of these steps would differ from the exact sum."""
+    net = _collapse_net()
+    X0 = np.tile(np.array([[1, 5, 0]], np.int32), (4, 1))
+    seed, step0, steps = 5, 1, 100
+    _, _, fired, times = oracle.ssa_run(net, X0, seed=seed, step0=step0, steps=steps,
+                                        want_times=True, period=period)
+    assert np.all(fired[0] == 0)
+    stale_differs = 0
+    for r in range(4):
+        x = X0[r].copy()
+        prev = 0.0
+        for i in range(steps):
+            j = int(fired[i, r])
+            assert j >= 0
+            a = oracle.propensities(net, x[None, :])[0]
+            w = oracle.draw(seed, TAU_BLOCK, r, step0 + i, oracle.TAG_SSA)[0]
+            exact = _exact_sum(a)
+            stale = sum(math.floor(Fraction(float(v)) * 2 ** 64) for v in a) / Fraction(2 ** 64)
+            stale_differs += i > 0 and float(stale) != float(exact)
+            assert times[i, r] == prev + oracle.neg_ln_uniform(int(w)) / float(exact), (r, i)
+            prev = times[i, r]
+            _stoich_apply(net, x, j)
+    assert stale_differs > 100
