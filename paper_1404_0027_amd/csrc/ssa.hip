@@ -288,6 +288,14 @@ __device__ __forceinline__ U128 readlane128(U128 x, int l)
     return r;
 }
 
+__device__ __forceinline__ double readlane_f64(double x, int l)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    return __longlong_as_double((long long)(
+        (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l) |
+        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l) << 32)));
+}
+
 // Sums mod 2^128 over the wavefront, over lanes 0..15, and over each 32-lane
 // half (the DPP patterns of the binary64 sums); every lane returns its sum.
 __device__ __forceinline__ U128 wave_sum_u128(U128 x)
@@ -462,6 +470,25 @@ __global__ __launch_bounds__(NW * 64, PROP ? 1 : 5) void k_ssa_run(RunArgs c)
     const bool maintain = period > 1;   // with period 1 the envelopes are not kept across steps
     const int L = ceil_log2_u32((uint32_t)M);
     double t = c.t[r];
+    // the time steps of a batch of up to 64 steps: lane k holds step b0 + k's
+    // Philox word and alpha_0; the logarithms and quotients are taken in
+    // parallel at the batch's end and added to t in step order
+    uint32_t bw = 0;
+    double ba = 1.0;
+    uint64_t fmask = 0;  // steps of the batch that fired
+    int64_t b0 = 0;
+    auto flush = [&](int64_t iend) {
+        const int n = (int)(iend - b0);
+        const double tau = ((fmask >> lane) & 1) ? neg_ln_u(bw, c.ln_tab) / ba : 0.0;
+        double tk = t;
+        for (int k = 0; k < n; ++k) {
+            if ((fmask >> k) & 1) t += readlane_f64(tau, k);
+            tk = lane == k ? t : tk;
+        }
+        if (c.times && lane < n) c.times[(b0 + lane) * c.R + r] = tk;
+        fmask = 0;
+        b0 = iend;
+    };
     U128 S{0, 0};        // sum of F at the scale Es (when have)
     int Es = kNoScale;
     bool have = false;
@@ -564,7 +591,15 @@ __global__ __launch_bounds__(NW * 64, PROP ? 1 : 5) void k_ssa_run(RunArgs c)
                 have = true;
             }
             const int sh = 127 - L - Es;
-            t += neg_ln_u(uniform_u32(tau_w), c.ln_tab) / wide_to_f64(S, sh);
+            {
+                const int slot = (int)(i - b0);
+                const double a0 = wide_to_f64(S, sh);
+                if (lane == slot) {
+                    bw = uniform_u32(tau_w);
+                    ba = a0;
+                }
+                fmask |= 1ull << slot;
+            }
             if (lane == 0) {
                 x[jr0] -= 1;
                 if (jr1 >= 0) x[jr1] -= 1;
@@ -638,8 +673,9 @@ __global__ __launch_bounds__(NW * 64, PROP ? 1 : 5) void k_ssa_run(RunArgs c)
             }
             wave_sync_lds();
         }
-        if (c.times && lane == 0) c.times[i * c.R + r] = t;
+        if (i + 1 - b0 == kWave) flush(i + 1);
     }
+    if (b0 < c.steps) flush(c.steps);
     for (int i = lane; i < N; i += kWave) gx[i] = x[i];
     if (lane == 0) c.t[r] = t;
 }
@@ -772,6 +808,26 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
     const bool maintain = period > 1;
     const int L = ceil_log2_u32((uint32_t)M);
     double t = live ? c.t[r] : 0.0;
+    // time steps batched as in k_ssa_run, 32 steps per half: lane hl of half
+    // h holds step b0 + hl of realization r; fmask bit 32 h + k marks a
+    // step that fired
+    uint32_t bw = 0;
+    double ba = 1.0;
+    uint64_t fmask = 0;
+    int64_t b0 = 0;
+    auto flush = [&](int64_t iend) {
+        const int n = (int)(iend - b0);
+        const double tau = ((fmask >> lane) & 1) ? neg_ln_u(bw, c.ln_tab) / ba : 0.0;
+        double tk = t;
+        for (int k = 0; k < n; ++k) {
+            const double t0 = readlane_f64(tau, k), t1 = readlane_f64(tau, 32 + k);
+            if ((fmask >> (k + (lane & 32))) & 1) t += h ? t1 : t0;
+            tk = hl == k ? t : tk;
+        }
+        if (c.times && live && hl < n) c.times[(b0 + hl) * c.R + r] = tk;
+        fmask = 0;
+        b0 = iend;
+    };
     U128 S{0, 0};        // each half's alpha_0 sum (k_ssa_run)
     int Es = kNoScale;
     bool have = false;
@@ -878,7 +934,15 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
                 }
             }
             const int sh = 127 - L - Es;
-            if (fire) t += neg_ln_u(tau_w, c.ln_tab) / wide_to_f64(S, sh);
+            {
+                const int slot = (int)(i - b0);
+                const double a0 = wide_to_f64(S, sh);
+                if (fire && hl == slot) {
+                    bw = tau_w;
+                    ba = a0;
+                }
+                fmask |= __ballot(fire && hl == slot);
+            }
             if (fire && hl == 0) {
                 x[jr0] -= 1;
                 if (jr1 >= 0) x[jr1] -= 1;
@@ -951,8 +1015,9 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
             }
             wave_sync_lds();
         }
-        if (c.times && live && hl == 0) c.times[i * c.R + r] = t;
+        if (i + 1 - b0 == 32) flush(i + 1);
     }
+    if (b0 < c.steps) flush(c.steps);
     if (live) {
         for (int i = hl; i < N; i += 32) gx[i] = x[i];
         if (hl == 0) c.t[r] = t;
