@@ -379,9 +379,11 @@ def bench_ssa(torch, np, arsel, workloads, lp=None, refresh: int = 1000, period:
            "mean_simulated_time": sim_t,
            "jump_chain_full_recompute_selections_per_s": round(R * steps / sec_chain, 1),
            "note": "per step: AR selection against the step's envelope, tau, stoichiometry, "
-                   "propensities of the affected reactions; envelopes and alpha_0 exact every "
+                   "propensities of the affected reactions; envelopes exact every "
                    f"{period} steps (one pass over the LDS-resident propensities), kept from "
-                   "the changed propensities between"}
+                   "the changed propensities between; alpha_0 of tau exact at every step "
+                   "(128-bit fixed-point sum kept from the changes, rounded once), so the "
+                   "times are bit-identical to the sequential definition"}
     if lp is None:
         return out
 
