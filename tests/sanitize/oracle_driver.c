@@ -41,6 +41,8 @@ int orc_ssa_run_proposal(int32_t *X, int64_t R, int64_t N, int64_t M, const int3
                          uint32_t period, const uint32_t *ids, uint64_t seed, uint64_t step0,
                          int64_t steps, uint32_t t_max, double *t, double *times,
                          int32_t *fired, int threads);
+double orc_neg_ln_uniform(uint32_t w);
+double orc_wide_alpha0(const float *a, int64_t M, int E);
 int orc_select_paper(const float *alpha, int64_t M, int64_t K, int64_t ld, double w,
                      uint64_t seed, uint64_t step, int32_t *index, int threads);
 int orc_select_ids(const float *alpha, int64_t M, int64_t n, const uint32_t *ids,
@@ -183,6 +185,23 @@ static void ssa(void)
     free(X); free(X0); free(alpha); free(rec); free(fired); free(t); free(times); free(Q);
 }
 
+/* the time step's pieces at the ends of their ranges: u = 2^-33 and
+ * 1 - 2^-33; alpha_0 of subnormals, of FLT_MAX entries, and under a scale
+ * far above the values (most weights drop to zero) */
+static void time_step(void)
+{
+    CHECK(orc_neg_ln_uniform(0u) > 22.8 && orc_neg_ln_uniform(0u) < 22.9);
+    CHECK(orc_neg_ln_uniform(0xFFFFFFFFu) > 0.0 && orc_neg_ln_uniform(0xFFFFFFFFu) < 1e-9);
+    const float sub[4] = {1e-45f, 3e-44f, 0.0f, 7e-40f};
+    CHECK(orc_wide_alpha0(sub, 4, -129) > 0.0);
+    float big[1000];
+    for (int i = 0; i < 1000; ++i) big[i] = 3.4028234e38f;
+    CHECK(orc_wide_alpha0(big, 1000, 128) > 3.4e41);
+    const float spread[5] = {1e30f, 1e-30f, 1e-40f, -1.0f, 5.0f};
+    CHECK(orc_wide_alpha0(spread, 5, 100) > 9.9e29);
+    CHECK(orc_wide_alpha0(spread, 5, 127) > 9.9e29);
+}
+
 int main(void)
 {
     uint32_t out[4];
@@ -193,6 +212,7 @@ int main(void)
     ragged();
     proposal();
     ssa();
+    time_step();
     if (fails) {
         fprintf(stderr, "%d checks failed\n", fails);
         return 1;
