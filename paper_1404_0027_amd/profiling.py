@@ -10,6 +10,13 @@
         batch (host-built work lists, indices only) with the given schedule
         (default 1024 8 0 4), for kernel traces and counters of its launches.
 
+    python -m paper_1404_0027_amd.profiling dense
+        Runs the dense selection 40 times on the benchmark's batch (R = 4096
+        realizations x M = 1029, SoA, lognormal(0,2) with 30% zeros, 32
+        rotating buffers; k_select_tile<16>) and 5 times on 10^6
+        realizations of the same law (k_select_tile<8>), for counters of both
+        launch shapes.
+
     python -m paper_1404_0027_amd.profiling summarize DB KERNEL_SUBSTR [--pmc]
         Prints per-kernel dispatch count and mean/min/max duration from a
         rocprofv3 kernel-trace database, or mean counter values per dispatch
@@ -87,6 +94,33 @@ def ragged_probe(sched=(1024, 8, 0, 4)) -> None:
           f"schedule {tuple(sched)}", flush=True)
 
 
+def dense_probe() -> None:
+    import torch
+
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_1404_0027_amd import arsel, workloads
+
+    M, R, nbuf = 1029, 4096, 32
+    bufs = torch.from_numpy(workloads.lognormal_soa(M=M, K=R, seed=2, buffers=nbuf)).cuda()
+    idx = torch.empty(R, dtype=torch.int32, device="cuda")
+    for s in range(40):
+        arsel.select(bufs[s % nbuf], M, R, R, arsel.SOA, seed=1, step=s, index=idx)
+    torch.cuda.synchronize()
+    del bufs
+    K = 1_000_000
+    g = torch.Generator(device="cuda").manual_seed(123)
+    a = torch.empty(M, K, device="cuda")
+    for r in range(0, M, 64):
+        blk = a[r:r + 64]
+        blk.log_normal_(0.0, 2.0, generator=g)
+        blk[torch.rand(blk.shape, device="cuda", generator=g) < 0.3] = 0.0
+    big = torch.empty(K, dtype=torch.int32, device="cuda")
+    for s in range(5):
+        arsel.select(a, M, K, K, arsel.SOA, seed=1, step=s, index=big)
+    torch.cuda.synchronize()
+    print(f"dense probe: 40 launches of {R} x {M}, 5 launches of {K} x {M}", flush=True)
+
+
 def _kernel_rows(db: str, substr: str):
     c = sqlite3.connect(db)
     return c.execute("select name, start, end from kernels where name like ?",
@@ -144,6 +178,8 @@ def main(argv: list[str]) -> int:
         return 2
     if argv[0] == "copy":
         copy_probe()
+    elif argv[0] == "dense":
+        dense_probe()
     elif argv[0] == "ragged":
         ragged_probe(tuple(int(x) for x in argv[1:5]) if len(argv) >= 5 else (1024, 8, 0, 4))
     elif argv[0] == "summarize":
