@@ -90,6 +90,19 @@ def test_run_times_after_a_propensity_collapse(gpu, period):
     _run_both_q(net, X0, np.full((37, 3), 7, np.uint32), seed=5, step0=1, steps=100, period=period)
 
 
+@pytest.mark.parametrize("kind", ["huge", "subnormal"])
+@pytest.mark.parametrize("period", [1, 7, 64])
+def test_run_times_at_the_ends_of_the_float_range(gpu, period, kind):
+    """alpha_max near FLT_MAX (scale exponent 127 and 128, negative shifts)
+    and all-subnormal propensities (shifts above 250)."""
+    from test_oracle_time_step import rated_network
+    net = rated_network(kind)
+    X0 = workloads.poisson_counts(N=24, R=37, seed=2)
+    _run_both(net, X0, seed=3, step0=0, steps=120, period=period)
+    Q = _shaped_q(net, X0)
+    _run_both_q(net, X0, Q, seed=3, step0=0, steps=120, period=period)
+
+
 def test_run_absorbs_and_overflowing_dependency_lists(gpu):
     # pure decay: absorbed after n firings (time stays, -1 recorded)
     dec = workloads.Network(N=2, r0=np.array([0], np.int32), r1=np.array([-1], np.int32),

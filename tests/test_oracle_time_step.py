@@ -131,23 +131,40 @@ def _stoich_apply(net, x, j):
         x[net.p1[j]] += 1
 
 
-@pytest.mark.parametrize("spread", [False, True])
+def rated_network(kind: str):
+    """The 24-species, 40-reaction test network with its own rates or with
+    rates spread over 60 binades, near FLT_MAX / 5000 (alpha_max at 2^127 ..
+    2^128, so the scale exponent reaches 128), or subnormal (every
+    propensity subnormal)."""
+    net = workloads.mass_action_network(N=24, M=40, seed=9)
+    rng = np.random.default_rng(5)
+    if kind == "spread":
+        rate = 2.0 ** rng.uniform(-45, 15, 40)
+    elif kind == "huge":
+        rate = 5e34 * rng.uniform(0.5, 1.0, 40)
+    elif kind == "subnormal":
+        rate = 2e-44 * rng.integers(1, 4, 40)
+    else:
+        return net
+    return dataclasses.replace(net, rate=rate.astype(np.float32))
+
+
+@pytest.mark.parametrize("kind", ["network", "spread", "huge", "subnormal"])
 @pytest.mark.parametrize("period", [1, 7])
-def test_run_times_step_by_step(period, spread):
+def test_run_times_step_by_step(period, kind):
     """Every recorded time is the previous one plus -ln u / alpha_0, rebuilt
     from the pinned parts: the state from the fired reactions, alpha_0 as the
     exact sum of that state's propensities rounded once, u from the pinned
     Philox stream.  With rates spread over 60 binades the binary64 sum in
-    index order differs from the exact one at most steps."""
-    net = workloads.mass_action_network(N=24, M=40, seed=9)
-    if spread:
-        rng = np.random.default_rng(5)
-        net = dataclasses.replace(net, rate=(2.0 ** rng.uniform(-45, 15, 40)).astype(np.float32))
+    index order differs from the exact one at most steps; the other rate
+    sets take the scale to both ends of the float range."""
+    net = rated_network(kind)
     X0 = workloads.poisson_counts(N=24, R=3, seed=2)
     ids = np.array([0, 5, 77], np.uint32)
     seed, step0, steps = 17, 3, 60
     _, t, fired, times = oracle.ssa_run(net, X0, seed=seed, step0=step0, steps=steps, ids=ids,
                                         want_times=True, period=period)
+    assert (fired >= 0).mean() > 0.9
     for r in range(3):
         x = X0[r].copy()
         prev = 0.0
