@@ -436,7 +436,7 @@ __device__ __forceinline__ void wave_sum_pair(int32_t &a, int32_t &b)
 // on the tag-1 stream.  An invalid propensity gives -2 and no positive one
 // -1 (both permanent: nothing fires), sum Q' >= 2^32 gives -4.
 template <int NW, bool PROP>
-__global__ __launch_bounds__(NW * 64, PROP ? 1 : 5) void k_ssa_run(RunArgs c)
+__global__ __launch_bounds__(NW * 64, PROP ? 1 : 6) void k_ssa_run(RunArgs c)
 {
     static_assert(kDepMax == kWave, "one dependency row per wavefront load");
     extern __shared__ int32_t lds_i[];
