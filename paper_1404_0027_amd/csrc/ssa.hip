@@ -809,15 +809,18 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
     const int L = ceil_log2_u32((uint32_t)M);
     double t = live ? c.t[r] : 0.0;
     // time steps batched as in k_ssa_run, 32 steps per half: lane hl of half
-    // h holds step b0 + hl of realization r; fmask bit 32 h + k marks a
-    // step that fired
+    // h holds step b0 + hl of realization r (its Philox word, and S with its
+    // shift, converted at the flush); fmask bit 32 h + k marks a step that
+    // fired
     uint32_t bw = 0;
-    double ba = 1.0;
+    U128 bs{1, 0};
+    int bsh = 0;
     uint64_t fmask = 0;
     int64_t b0 = 0;
     auto flush = [&](int64_t iend) {
         const int n = (int)(iend - b0);
-        const double tau = ((fmask >> lane) & 1) ? neg_ln_u(bw, c.ln_tab) / ba : 0.0;
+        const double tau =
+            ((fmask >> lane) & 1) ? neg_ln_u(bw, c.ln_tab) / wide_to_f64(bs, bsh) : 0.0;
         double tk = t;
         for (int k = 0; k < n; ++k) {
             const double t0 = readlane_f64(tau, k), t1 = readlane_f64(tau, 32 + k);
@@ -936,10 +939,10 @@ __global__ __launch_bounds__(NW * 64) void k_ssa_run_pair(RunArgs c)
             const int sh = 127 - L - Es;
             {
                 const int slot = (int)(i - b0);
-                const double a0 = wide_to_f64(S, sh);
                 if (fire && hl == slot) {
                     bw = tau_w;
-                    ba = a0;
+                    bs = S;
+                    bsh = sh;
                 }
                 fmask |= __ballot(fire && hl == slot);
             }
