@@ -426,9 +426,10 @@ __device__ __forceinline__ void wave_sum_pair(int32_t &a, int32_t &b)
 // update of the affected reactions keeps the counts and the running maxima
 // B and C, so a step reads only its candidates and the changed reactions.
 // alpha_0 of the time step is the 128-bit fixed-point sum S (above), kept
-// from the changed reactions' differences at every period.  B >= alpha_max and C >= max_j
-// alpha_j / Q'_j keep each step's law alpha_j / alpha_0; the fallback still
-// uses the exact alpha_max.  p = 1 takes the pass at every step.
+// from the changed reactions' differences at every period.  B >= alpha_max
+// and C >= max_j alpha_j / Q'_j keep each step's law alpha_j / alpha_0; the
+// fallback still uses the exact alpha_max.  p = 1 takes the pass at every
+// step.
 //
 // PROP = false selects with uniform AR on the tag-2 stream (the jump
 // chain's); PROP = true with the integer proposal Q'_j = max(Q_j, qfloor, 1)
