@@ -157,6 +157,65 @@ def test_run_resumes_at_period_boundaries(gpu):
     assert torch.equal(ta, tb)
 
 
+def test_run_graph_capture_replays_match_eager(gpu):
+    """Full runs captured in one HIP graph (uniform with maintained envelopes,
+    uniform exact every step, proposal), replayed four times from reset states
+    with eager runs between the replays: every replay equals the oracle
+    (states, times, selections)."""
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    X0 = workloads.poisson_counts(N=64, R=37, seed=5)
+    Q = _shaped_q(net, X0)
+    dn = learned.DeviceNetwork(net)
+    cases = [dict(period=64), dict(period=1), dict(period=16, Q=Q, qfloor=40)]
+    refs = []
+    for cfg in cases:
+        xo, to, fo, tmo = oracle.ssa_run(net, X0, seed=9, step0=5, steps=150, want_times=True,
+                                         threads=8, **cfg)
+        refs.append((xo, to, fo, tmo))
+    Qd = torch.from_numpy(Q.view(np.int32)).cuda()
+    X0d = torch.from_numpy(X0).cuda()
+    Xs = [X0d.clone() for _ in cases]
+    ts = [torch.zeros(37, dtype=torch.float64, device="cuda") for _ in cases]
+
+    def run_all():
+        out = []
+        for X, t, cfg in zip(Xs, ts, cases):
+            kw = dict(period=cfg["period"])
+            if "Q" in cfg:
+                kw.update(Q=Qd, qfloor=cfg["qfloor"])
+            out.append(dn.run(X, t, seed=9, step0=5, steps=150, want_fired=True,
+                              want_times=True, **kw))
+        return out
+
+    run_all()                       # sizes the context's buffers before the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(g, stream=cap, capture_error_mode="relaxed"):
+            outs = run_all()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for X, t in zip(Xs, ts):
+            X.copy_(X0d)
+            t.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, ((fired, times), (xo, to, fo, tmo)) in enumerate(zip(outs, refs)):
+            assert np.array_equal(Xs[i].cpu().numpy(), xo), ("states", i, rep)
+            np.testing.assert_array_equal(ts[i].cpu().numpy(), to)
+            assert np.array_equal(fired.cpu().numpy(), fo), ("selections", i, rep)
+            np.testing.assert_array_equal(times.cpu().numpy(), tmo)
+        # eager work between replays, on other buffers and another network
+        other = workloads.mass_action_network(N=32, M=70, seed=rep)
+        Xe = torch.from_numpy(workloads.poisson_counts(N=32, R=9, seed=rep)).cuda()
+        learned.DeviceNetwork(other).run(Xe, torch.zeros(9, dtype=torch.float64, device="cuda"),
+                                         seed=1, step0=0, steps=40, period=8)
+        torch.cuda.synchronize()
+
+
 def _sample_ids(R, n, seed):
     """n realization ids: half even, half odd (the two halves of a wavefront in
     the two-realizations-per-wavefront kernel), plus the first and the last."""
