@@ -444,7 +444,10 @@ __global__ __launch_bounds__(kSoftmaxWaves * 64) void k_softmax_quant(
     const int64_t r = (int64_t)blockIdx.x * kSoftmaxWaves + wave;
     if (r < R) {
         float *ce = loss ? &ce_row[wave] : nullptr;
-        if (M <= 64 * kSoftmaxPer)
+        if (M <= 64 * 17)           // M = 1029 and below: 17 elements per lane
+            softmax_row<17>(Z + r * ldz, alpha + r * M, r, M, L, q_out, Q_out, dz_b, dz_f, lddz,
+                            scale, ce, lane);
+        else if (M <= 64 * kSoftmaxPer)
             softmax_row<kSoftmaxPer>(Z + r * ldz, alpha + r * M, r, M, L, q_out, Q_out, dz_b,
                                      dz_f, lddz, scale, ce, lane);
         else
