@@ -79,16 +79,22 @@ __device__ inline Outcome wave_proposal_rounds(const float *sa, const uint32_t *
     const int lane = lane_id();
     const uint32_t thresh = lemire_threshold(S);
     const uint32_t rounds = (uint32_t)(((uint64_t)t_max + kRoundTrials - 1) / kRoundTrials);
-    auto pick = [&](uint32_t V) {
-        uint32_t lo = 0, hi = M - 1;   // least j with P_j > V
-        while (lo < hi) {
-            const uint32_t mid = lo + ((hi - lo) >> 1);
-            if (sp[mid] > V)
-                hi = mid;
-            else
-                lo = mid + 1;
+    // least j with P_j > V for both trials of a lane: P is nondecreasing, so
+    // that j is the number of P_j <= V, found by adding power-of-two steps
+    // (the same number of steps in every lane; the two searches' loads are
+    // independent and overlap)
+    uint32_t top = 1;
+    while (2 * top <= M) top *= 2;
+    auto pick2 = [&](uint32_t Va, uint32_t Vb, uint32_t &ja, uint32_t &jb) {
+        uint32_t pa = 0, pb = 0;
+        for (uint32_t step = top; step > 0; step >>= 1) {
+            const uint32_t ia = pa + step, ib = pb + step;
+            const uint32_t xa = sp[min(ia, M) - 1], xb = sp[min(ib, M) - 1];
+            if (ia <= M && xa <= Va) pa = ia;
+            if (ib <= M && xb <= Vb) pb = ib;
         }
-        return lo;
+        ja = min(pa, M - 1);
+        jb = min(pb, M - 1);
     };
     auto accept = [&](uint32_t j, uint32_t uw) {
         const double uc = grid_u(uw) * cplus;
@@ -105,7 +111,8 @@ __device__ inline Outcome wave_proposal_rounds(const float *sa, const uint32_t *
         uint32_t va, vb;
         const bool oka = lemire(w.w0, S, thresh, va) && ta < t_max;
         const bool okb = lemire(w.w2, S, thresh, vb) && ta + 1 < t_max;
-        const uint32_t ja = pick(va), jb = pick(vb);
+        uint32_t ja, jb;
+        pick2(va, vb, ja, jb);
         const bool acca = oka && accept(ja, w.w1);
         const bool accb = okb && accept(jb, w.w3);
         const uint64_t ma = __ballot(acca), mb = __ballot(accb);
