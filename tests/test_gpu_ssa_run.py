@@ -103,6 +103,17 @@ def test_run_times_at_the_ends_of_the_float_range(gpu, period, kind):
     _run_both_q(net, X0, Q, seed=3, step0=0, steps=120, period=period)
 
 
+@pytest.mark.parametrize("period", [1, 16])
+@pytest.mark.parametrize("steps", [1, 31, 32, 33, 63, 64, 65, 128, 129])
+def test_run_time_batches_at_their_boundaries(gpu, period, steps):
+    """The time step is taken in batches of 64 steps (32 per half with two
+    realizations per wavefront): runs ending just before, at and after a
+    batch boundary record the oracle's times."""
+    net = workloads.mass_action_network(N=64, M=100, seed=4)
+    X0 = workloads.poisson_counts(N=64, R=37, seed=5)
+    _run_both(net, X0, seed=12, step0=7, steps=steps, period=period)
+
+
 def test_run_absorbs_and_overflowing_dependency_lists(gpu):
     # pure decay: absorbed after n firings (time stays, -1 recorded)
     dec = workloads.Network(N=2, r0=np.array([0], np.int32), r1=np.array([-1], np.int32),
