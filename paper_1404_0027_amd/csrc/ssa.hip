@@ -1141,8 +1141,9 @@ static int ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps
         return hipGetLastError() == hipSuccess ? ARSEL_OK : ARSEL_ERR_HIP;
     }
     // four realizations per workgroup for uniform AR; with a proposal one per
-    // workgroup, whose 64-thread workgroups pack the LDS tighter (14 against 12
-    // realizations per CU at N = 641, M = 1029; measured 4-9% faster)
+    // workgroup, whose 64-thread workgroups pack the LDS tighter (up to 15
+    // against 12 realizations per CU at N = 641, M = 1029; measured 4-9%
+    // faster)
     const bool four = !prop && per_wave * 4 <= ctx->tile_lds_bytes;
     const dim3 grid(four ? (R + 3) / 4 : R), block(four ? 256 : 64);
     const size_t lds = per_wave * (four ? 4 : 1);
