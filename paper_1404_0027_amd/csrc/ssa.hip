@@ -1148,10 +1148,7 @@ static int ssa_run(arsel_ctx *ctx, const arsel_network *net, const int32_t *deps
     const dim3 grid(four ? (R + 3) / 4 : R), block(four ? 256 : 64);
     const size_t lds = per_wave * (four ? 4 : 1);
     if (prop) {
-        if (four)
-            hipLaunchKernelGGL((k_ssa_run<4, true>), grid, block, lds, s, c);
-        else
-            hipLaunchKernelGGL((k_ssa_run<1, true>), grid, block, lds, s, c);
+        hipLaunchKernelGGL((k_ssa_run<1, true>), grid, block, lds, s, c);
     } else {
         if (four)
             hipLaunchKernelGGL((k_ssa_run<4, false>), grid, block, lds, s, c);
