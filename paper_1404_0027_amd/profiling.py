@@ -17,6 +17,12 @@
         realizations of the same law (k_select_tile<8>), for counters of both
         launch shapes.
 
+    python -m paper_1404_0027_amd.profiling ssa
+        Runs the full SSA on the benchmark's network (N = 641, M = 1029, counts
+        Poisson(50)), R = 16384 realizations x 2000 steps, once with envelopes
+        maintained between exact steps every 64 (k_ssa_run_pair) and once
+        exact at every step (k_ssa_run), for counters of both run kernels.
+
     python -m paper_1404_0027_amd.profiling summarize DB KERNEL_SUBSTR [--pmc]
         Prints per-kernel dispatch count and mean/min/max duration from a
         rocprofv3 kernel-trace database, or mean counter values per dispatch
@@ -121,6 +127,24 @@ def dense_probe() -> None:
     print(f"dense probe: 40 launches of {R} x {M}, 5 launches of {K} x {M}", flush=True)
 
 
+def ssa_probe() -> None:
+    import torch
+
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_1404_0027_amd import learned, workloads
+
+    net = workloads.mass_action_network()
+    dn = learned.DeviceNetwork(net)
+    R, steps = 16384, 2000
+    X0 = torch.from_numpy(workloads.poisson_counts(N=net.N, R=R, seed=5)).cuda()
+    for period in (64, 1):
+        X = X0.clone()
+        t = torch.zeros(R, dtype=torch.float64, device="cuda")
+        dn.run(X, t, seed=1, step0=0, steps=steps, period=period)
+    torch.cuda.synchronize()
+    print(f"ssa probe: {R} realizations x {steps} steps at periods 64 and 1", flush=True)
+
+
 def _kernel_rows(db: str, substr: str):
     c = sqlite3.connect(db)
     return c.execute("select name, start, end from kernels where name like ?",
@@ -180,6 +204,8 @@ def main(argv: list[str]) -> int:
         copy_probe()
     elif argv[0] == "dense":
         dense_probe()
+    elif argv[0] == "ssa":
+        ssa_probe()
     elif argv[0] == "ragged":
         ragged_probe(tuple(int(x) for x in argv[1:5]) if len(argv) >= 5 else (1024, 8, 0, 4))
     elif argv[0] == "summarize":
